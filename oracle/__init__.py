@@ -1,0 +1,24 @@
+"""CPU oracle of the VELO reconstruction path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  It wraps `libvelo_oracle.so`, built from
+`velo_oracle.c` (plain C, binary32 arithmetic without contraction), and
+shares no code with the HIP implementation.
+"""
+from .oracle import (  # noqa: F401
+    DEFAULT_PARAMS,
+    EV_BAD_WORD,
+    EV_DUPLICATE,
+    EV_HOLE,
+    EV_LAYER_ORDER,
+    EV_OVERFLOW,
+    MAX_CANDIDATES,
+    build,
+    cluster,
+    find_tracks,
+    fit,
+    fit_points,
+    layer_z,
+    lib_path,
+    reconstruct,
+)

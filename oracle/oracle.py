@@ -1,0 +1,211 @@
+"""ctypes binding of the C oracle (test infrastructure only).
+
+Array conventions follow `velo_oracle.h`: hits live at absolute slot
+offsets[e] + layer_start[e, l] + rank, tracks at floor(offsets[e] / 3) + t.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "velo_oracle.c")
+_LIB = os.path.join(_HERE, "libvelo_oracle.so")
+
+EV_BAD_WORD = 1
+EV_LAYER_ORDER = 2
+EV_DUPLICATE = 4
+EV_HOLE = 8
+EV_OVERFLOW = 16
+MAX_CANDIDATES = 65536
+
+# Default cut and filter constants (a reading of the paper, which gives only
+# the 400 MeV transverse momentum of the scattering model).
+DEFAULT_PARAMS = dict(
+    max_t=0.4, sin2_phi=9e-4, s_seed=0.025, s_fwd=0.04, max_skip=1,
+    sigma_meas=0.055 / 12 ** 0.5, pt0_mev=400.0, x_over_x0=5.94e-4, qc3=4.0, qc4=10.0,
+)
+
+
+class _Params(C.Structure):
+    _fields_ = [("max_t", C.c_float), ("sin2_phi", C.c_float), ("s_seed", C.c_float),
+                ("s_fwd", C.c_float), ("max_skip", C.c_int32), ("sigma_meas", C.c_float),
+                ("pt0_mev", C.c_float), ("x_over_x0", C.c_float), ("qc3", C.c_float),
+                ("qc4", C.c_float)]
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off",
+                               "-fno-fast-math", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.velo_oracle_cluster.restype = C.c_uint32
+        lib.velo_oracle_cluster.argtypes = [P, P, C.c_uint32] + [P] * 8
+        lib.velo_oracle_find_tracks.restype = None
+        lib.velo_oracle_find_tracks.argtypes = [P, P, P, P, P, P, C.c_uint32, P, P, P, P, P]
+        lib.velo_oracle_fit.restype = None
+        lib.velo_oracle_fit.argtypes = [P, P, P, P, C.c_uint32, P, P, P, P] + [P] * 10
+        lib.velo_oracle_fit_points.restype = C.c_int32
+        lib.velo_oracle_fit_points.argtypes = [P, P, P, P, C.c_int32, P, P, P, P, P]
+        lib.velo_oracle_layer_z.restype = C.c_float
+        lib.velo_oracle_layer_z.argtypes = [C.c_int32]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray, off: int = 0):
+    return C.c_void_p(a.ctypes.data + off * a.itemsize)
+
+
+def _params(params) -> _Params:
+    d = dict(DEFAULT_PARAMS)
+    if params:
+        d.update(params)
+    return _Params(**{k: d[k] for k, _ in _Params._fields_})
+
+
+def layer_z(l: int) -> float:
+    return float(_L().velo_oracle_layer_z(int(l)))
+
+
+def cluster(pixels, offsets, events=None) -> dict:
+    """Cluster all events (or the half-open event range `events`)."""
+    pixels = np.ascontiguousarray(pixels, np.uint32)
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    e0, e1 = (0, E) if events is None else events
+    N = max(int(offsets[-1]), 1)
+    out = dict(x=np.zeros(N, np.float32), y=np.zeros(N, np.float32),
+               key=np.zeros(N, np.uint32), aux=np.zeros(N, np.uint32),
+               layer_start=np.zeros((E, 27), np.uint32), layer_nhits=np.zeros((E, 26), np.uint32),
+               n_hits=np.zeros(E, np.uint32), status=np.zeros(E, np.uint32))
+    cluster_into(pixels, offsets, e0, e1, out)
+    return out
+
+
+def cluster_into(pixels, offsets, e0, e1, out):
+    if e1 <= e0:
+        return
+    _L().velo_oracle_cluster(_p(pixels), _p(offsets, e0), e1 - e0,
+                             _p(out["x"]), _p(out["y"]), _p(out["key"]), _p(out["aux"]),
+                             _p(out["layer_start"], 27 * e0), _p(out["layer_nhits"], 26 * e0),
+                             _p(out["n_hits"], e0), _p(out["status"], e0))
+
+
+def find_tracks(hits: dict, offsets, params=None, events=None) -> dict:
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    e0, e1 = (0, E) if events is None else events
+    cap = max(int(offsets[-1]) // 3, 1)
+    out = dict(n_tracks=np.zeros(E, np.uint32), nhits=np.zeros(cap, np.uint8),
+               hit_idx=np.zeros((cap, 26), np.uint32), status=np.zeros(E, np.uint32))
+    find_into(hits, offsets, e0, e1, _params(params), out)
+    return out
+
+
+def find_into(hits, offsets, e0, e1, P, out):
+    if e1 <= e0:
+        return
+    _L().velo_oracle_find_tracks(_p(hits["x"]), _p(hits["y"]), _p(hits["key"]),
+                                 _p(hits["layer_start"], 27 * e0), _p(hits["layer_nhits"], 26 * e0),
+                                 _p(offsets, e0), e1 - e0, C.byref(P),
+                                 _p(out["n_tracks"], e0), _p(out["nhits"]), _p(out["hit_idx"]),
+                                 _p(out["status"], e0))
+
+
+def fit(hits: dict, tracks: dict, offsets, params=None, events=None) -> dict:
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    e0, e1 = (0, E) if events is None else events
+    cap = max(int(offsets[-1]) // 3, 1)
+    f = lambda: np.zeros(cap, np.float32)  # noqa: E731
+    out = dict(x=f(), y=f(), z=f(), tx=f(), ty=f(), cov_x=np.zeros((cap, 3), np.float32),
+               cov_y=np.zeros((cap, 3), np.float32), chi2=f(), ndof=np.zeros(cap, np.int32),
+               accepted=np.zeros(cap, np.uint8))
+    fit_into(hits, tracks, offsets, e0, e1, _params(params), out)
+    return out
+
+
+def fit_into(hits, tracks, offsets, e0, e1, P, out):
+    if e1 <= e0:
+        return
+    _L().velo_oracle_fit(_p(hits["x"]), _p(hits["y"]), _p(hits["key"]), _p(offsets, e0), e1 - e0,
+                         _p(tracks["n_tracks"], e0), _p(tracks["nhits"]), _p(tracks["hit_idx"]),
+                         C.byref(P), _p(out["x"]), _p(out["y"]), _p(out["z"]), _p(out["tx"]),
+                         _p(out["ty"]), _p(out["cov_x"]), _p(out["cov_y"]), _p(out["chi2"]),
+                         _p(out["ndof"]), _p(out["accepted"]))
+
+
+def fit_points(hx, hy, hz, hlayer, params=None):
+    """Fit one track from explicit hit coordinates (decreasing z)."""
+    hx = np.ascontiguousarray(hx, np.float32)
+    hy = np.ascontiguousarray(hy, np.float32)
+    hz = np.ascontiguousarray(hz, np.float32)
+    hl = np.ascontiguousarray(hlayer, np.int32)
+    o5 = np.zeros(5, np.float32)
+    cx = np.zeros(3, np.float32)
+    cy = np.zeros(3, np.float32)
+    chi2 = np.zeros(1, np.float32)
+    P = _params(params)
+    nd = _L().velo_oracle_fit_points(_p(hx), _p(hy), _p(hz), _p(hl), len(hx), C.byref(P),
+                                     _p(o5), _p(cx), _p(cy), _p(chi2))
+    return dict(x=o5[0], y=o5[1], z=o5[2], tx=o5[3], ty=o5[4], cov_x=cx, cov_y=cy,
+                chi2=float(chi2[0]), ndof=int(nd))
+
+
+def reconstruct(pixels, offsets, params=None, events=None, threads: int = 1) -> dict:
+    """cluster -> find -> fit on a thread pool over contiguous event ranges."""
+    pixels = np.ascontiguousarray(pixels, np.uint32)
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    e0, e1 = (0, E) if events is None else events
+    N = max(int(offsets[-1]), 1)
+    cap = max(int(offsets[-1]) // 3, 1)
+    P = _params(params)
+    hits = dict(x=np.zeros(N, np.float32), y=np.zeros(N, np.float32),
+                key=np.zeros(N, np.uint32), aux=np.zeros(N, np.uint32),
+                layer_start=np.zeros((E, 27), np.uint32), layer_nhits=np.zeros((E, 26), np.uint32),
+                n_hits=np.zeros(E, np.uint32), status=np.zeros(E, np.uint32))
+    tracks = dict(n_tracks=np.zeros(E, np.uint32), nhits=np.zeros(cap, np.uint8),
+                  hit_idx=np.zeros((cap, 26), np.uint32), status=np.zeros(E, np.uint32))
+    f = lambda: np.zeros(cap, np.float32)  # noqa: E731
+    states = dict(x=f(), y=f(), z=f(), tx=f(), ty=f(), cov_x=np.zeros((cap, 3), np.float32),
+                  cov_y=np.zeros((cap, 3), np.float32), chi2=f(), ndof=np.zeros(cap, np.int32),
+                  accepted=np.zeros(cap, np.uint8))
+
+    def run(a, b):
+        cluster_into(pixels, offsets, a, b, hits)
+        find_into(hits, offsets, a, b, P, tracks)
+        fit_into(hits, tracks, offsets, a, b, P, states)
+
+    if threads <= 1 or e1 - e0 < 2:
+        run(e0, e1)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        step = max(1, (e1 - e0 + 4 * threads - 1) // (4 * threads))
+        ranges = [(a, min(a + step, e1)) for a in range(e0, e1, step)]
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda r: run(*r), ranges))
+    return dict(hits=hits, tracks=tracks, states=states)

@@ -1,0 +1,115 @@
+/*
+ * velo_oracle.h -- plain CPU oracle of the VELO reconstruction path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to judge the HIP
+ * implementation; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no source with the HIP library.
+ *
+ * What it computes (paper: "Allen: A high level trigger on GPUs for LHCb",
+ * Sec. 2.3.1 "Velo detector"; Sec. 2.2 for the event-level data layout):
+ *   velo_oracle_cluster      decode raw pixel words and group the fired
+ *                            pixels of each plane into 8-connected clusters
+ *                            (the connected-component labelling of Sec. 2.3.1)
+ *   velo_oracle_find_tracks  straight-line search by triplet: seeds of three
+ *                            hits on consecutive planes, extended plane by
+ *                            plane (Sec. 2.3.1, second paragraph)
+ *   velo_oracle_fit          x/y-independent simple Kalman filter with a
+ *                            constant 400 MeV transverse momentum for the
+ *                            scattering noise, then extrapolation to the
+ *                            point of closest approach to the beamline
+ *                            (Sec. 2.3.1, third and fourth paragraphs)
+ *
+ * Every rule the paper leaves open (raw format, connectivity, cuts, tie
+ * breaks, filter initialisation) is a written reading of the paper; the
+ * list lives with the project's design notes.  Floating point is IEEE
+ * binary32 in the order written, compiled without contraction, because the
+ * same decisions (cuts, sorting) are taken in binary32 by the GPU code.
+ *
+ * All pointers are host pointers.  Arrays indexed "absolute" use the
+ * position of the data in the whole batch (pixel offsets), so a caller may
+ * pass `offsets + e0` and a sub-range of events.
+ */
+#ifndef VELO_ORACLE_H
+#define VELO_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VO_N_LAYERS 26
+
+/* per-event status bits */
+#define VO_EV_BAD_WORD     1u  /* bit 31 set, layer >= 26, row/col >= 1536 or charge 0 */
+#define VO_EV_LAYER_ORDER  2u  /* layer field decreases somewhere along the event's words */
+#define VO_EV_DUPLICATE    4u  /* two words with the same address (only reported when no other bit is set) */
+#define VO_EV_HOLE         8u  /* an otherwise valid word addresses an inactive (beam-hole) pixel */
+#define VO_EV_OVERFLOW    16u  /* a track-finding step exceeded VO_MAX_CANDIDATES candidates */
+
+/* Upper bound on the candidates (seed triplets, or track-hit pairs) of one
+   track-finding step.  An event exceeding it is flagged and gets no tracks. */
+#define VO_MAX_CANDIDATES 65536u
+
+typedef struct {
+    float max_t;        /* |tx|,|ty| limit of a seed doublet */
+    float sin2_phi;     /* sin^2 of the largest azimuth difference of a seed doublet */
+    float s_seed;       /* mm^2, squared distance of the third seed hit to the doublet line */
+    float s_fwd;        /* mm^2, squared distance of a forwarded hit to the track line */
+    int32_t max_skip;   /* planes a track may miss in a row before it is closed */
+    float sigma_meas;   /* mm, hit resolution */
+    float pt0_mev;      /* transverse momentum assumed for scattering noise */
+    float x_over_x0;    /* radiation length fraction of one plane */
+    float qc3, qc4;     /* chi2/ndof limits of 3-hit / >=4-hit tracks */
+} vo_params;
+
+/* Clustering of events [0, n_events).
+   pixels        raw words, absolute positions
+   offsets[n+1]  absolute word offsets (uint64)
+   out hits      x, y, key, aux at absolute slot offsets[e] + layer_start[e][l] + rank
+   layer_start   [n*27] event-relative first slot of each layer (= index of the
+                 layer's first word in the event); [26] = words in the event
+   layer_nhits   [n*26] clusters per layer
+   n_hits        [n]    clusters per event
+   status        [n]    VO_EV_* bits; an event with any bit set has no hits and
+                        all its layer_start / layer_nhits entries are 0
+   returns the OR of all statuses */
+uint32_t velo_oracle_cluster(const uint32_t* pixels, const uint64_t* offsets, uint32_t n_events,
+                             float* x, float* y, uint32_t* key, uint32_t* aux,
+                             uint32_t* layer_start, uint32_t* layer_nhits,
+                             uint32_t* n_hits, uint32_t* status);
+
+/* Track finding of events [0, n_events) on clustered hits.
+   Track slots of event e start at floor(offsets[e]/3) (absolute).
+   n_tracks[n], trk_nhits[slot], hit_idx[slot*26 + j] = event-relative hit slot of
+   the track's j-th hit, in decreasing z.  trk_status[n] = 0 or VO_EV_OVERFLOW.
+   Tracks of an event are ordered by decreasing key of their first hit. */
+void velo_oracle_find_tracks(const float* x, const float* y, const uint32_t* key,
+                             const uint32_t* layer_start, const uint32_t* layer_nhits,
+                             const uint64_t* offsets, uint32_t n_events, const vo_params* p,
+                             uint32_t* n_tracks, uint8_t* trk_nhits, uint32_t* hit_idx,
+                             uint32_t* trk_status);
+
+/* Fit of all tracks of events [0, n_events).  State outputs at track slots:
+   x, y, z (beamline point of closest approach), tx, ty, cov_x[3*slot] =
+   (var x, cov x-tx, var tx), cov_y likewise, chi2, ndof, accepted (plain cut). */
+void velo_oracle_fit(const float* x, const float* y, const uint32_t* key,
+                     const uint64_t* offsets, uint32_t n_events,
+                     const uint32_t* n_tracks, const uint8_t* trk_nhits, const uint32_t* hit_idx,
+                     const vo_params* p,
+                     float* sx, float* sy, float* sz, float* stx, float* sty,
+                     float* cov_x, float* cov_y, float* chi2, int32_t* ndof, uint8_t* accepted);
+
+/* Fit of one track given its hit coordinates directly (decreasing z).
+   Used by the closed-form checks of the filter.  out[0..4] = x, y, z, tx, ty;
+   cov_x[3], cov_y[3], *chi2, returns ndof. */
+int32_t velo_oracle_fit_points(const float* hx, const float* hy, const float* hz,
+                               const int32_t* hlayer, int32_t n, const vo_params* p,
+                               float* out5, float* cov_x, float* cov_y, float* chi2);
+
+/* float z of layer l */
+float velo_oracle_layer_z(int32_t l);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

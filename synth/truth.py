@@ -1,0 +1,183 @@
+"""Generator-truth matching and tracking metrics (test / benchmark infrastructure).
+
+Definitions (paper Sec. 3.1): a track is correctly reconstructed when at least
+70 % of its hits belong to one simulated particle; a particle is
+reconstructible when it has hits on at least three different planes.
+Readings for the rest: the truth of a hit is the particle that contributes
+most charge to its pixels (ties to the lower id; noise pixels count for no
+particle and a noise-majority hit has no particle); ghost rate = accepted
+tracks matched to no particle / accepted tracks; clone rate =
+(matched tracks - matched particles) / matched tracks.
+
+Hit membership (which raw pixels form the hit with a given key) is computed
+here with scipy's graph connected components, independently of both the
+oracle and the GPU library.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+
+def pixel_components(pixels: np.ndarray, offsets: np.ndarray):
+    """Label the 8-connected pixel groups of every (event, plane).
+
+    Returns (label[N], key_of_label[L]) where key is the group's smallest
+    27-bit pixel address (layer << 22 | row << 11 | col).
+    """
+    pixels = np.asarray(pixels, np.uint32)
+    n = len(pixels)
+    if n == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.uint32)
+    ev = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets.astype(np.int64)))
+    addr = (pixels & 0x07FFFFFF).astype(np.int64)
+    g = (ev.astype(np.int64) << 27) | addr          # global address, unique per pixel
+    order = np.argsort(g, kind="stable")
+    gs = g[order]
+    rows, cols = [], []
+    # forward neighbours: (r, c+1), (r+1, c-1), (r+1, c), (r+1, c+1)
+    col = gs & 0x7FF
+    row = (gs >> 11) & 0x7FF
+    for dr, dc in ((0, 1), (1, -1), (1, 0), (1, 1)):
+        ok = (col + dc >= 0) & (col + dc < 1536) & (row + dr < 1536)
+        tgt = gs + (dr << 11) + dc
+        j = np.searchsorted(gs, tgt)
+        j = np.minimum(j, n - 1)
+        hit = ok & (gs[j] == tgt)
+        rows.append(np.nonzero(hit)[0])
+        cols.append(j[hit])
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    A = coo_matrix((np.ones(len(r), np.int8), (r, c)), shape=(n, n))
+    _, lab_sorted = connected_components(A, directed=False)
+    label = np.empty(n, np.int64)
+    label[order] = lab_sorted
+    nl = int(label.max()) + 1
+    key = np.full(nl, np.iinfo(np.int64).max, np.int64)
+    np.minimum.at(key, label, addr)
+    return label, key.astype(np.uint32)
+
+
+class Truth:
+    """Per-event map hit key -> particle, and particle reconstructibility."""
+
+    def __init__(self, batch):
+        self.batch = batch
+        label, lkey = pixel_components(batch.pixels, batch.offsets)
+        E = batch.n_events
+        ev = np.repeat(np.arange(E), np.diff(batch.offsets.astype(np.int64)))
+        pid = batch.pix_pid.astype(np.int64)
+        q = batch.pix_q.astype(np.int64)
+        # charge per (label, particle); noise (-1) never wins
+        real = pid >= 0
+        lp = label[real] * (1 << 24) + pid[real]
+        uniq, inv = np.unique(lp, return_inverse=True)
+        qs = np.bincount(inv, weights=q[real])
+        lab_u = uniq >> 24
+        pid_u = uniq & ((1 << 24) - 1)
+        # noise charge per label
+        qn = np.bincount(label[~real], weights=q[~real], minlength=len(lkey))
+        # best particle per label: max charge, then lowest id
+        o = np.lexsort((pid_u, -qs, lab_u))
+        first = np.ones(len(o), bool)
+        first[1:] = lab_u[o][1:] != lab_u[o][:-1]
+        best_lab = lab_u[o][first]
+        best_pid = pid_u[o][first]
+        best_q = qs[o][first]
+        lab_pid = np.full(len(lkey), -1, np.int64)
+        keep = best_q > qn[best_lab]
+        lab_pid[best_lab[keep]] = best_pid[keep]
+        lab_ev = np.zeros(len(lkey), np.int64)
+        lab_ev[label] = ev
+        self.lab_ev = lab_ev
+        self.lab_key = lkey
+        self.lab_pid = lab_pid
+        # lookup (event, key) -> particle
+        self._gk = (lab_ev << 27) | lkey.astype(np.int64)
+        o = np.argsort(self._gk)
+        self._gk = self._gk[o]
+        self._gp = lab_pid[o]
+        # reconstructible particles: hits on >= 3 distinct planes
+        has = lab_pid >= 0
+        pl = (lab_ev[has] << 40) | (lab_pid[has] << 5) | (lkey[has].astype(np.int64) >> 22)
+        pl = np.unique(pl)
+        part = pl >> 5
+        up, cnt = np.unique(part, return_counts=True)
+        self.reco_ev = up >> 35
+        self.reco_pid = up & ((1 << 35) - 1)
+        self.reco_ok = cnt >= 3
+        self.n_reconstructible = int(np.count_nonzero(self.reco_ok))
+
+    def hit_particle(self, ev: np.ndarray, key: np.ndarray) -> np.ndarray:
+        gk = (np.asarray(ev, np.int64) << 27) | np.asarray(key, np.int64)
+        j = np.searchsorted(self._gk, gk)
+        j = np.minimum(j, len(self._gk) - 1)
+        out = np.where(self._gk[j] == gk, self._gp[j], -1)
+        return out
+
+
+def track_list(tracks: dict, hits: dict, offsets: np.ndarray):
+    """Flatten per-event track outputs: (event, slot, n_hits, keys[T, 26] (0 pad))."""
+    offsets = np.asarray(offsets, np.int64)
+    E = len(offsets) - 1
+    base = offsets[:-1] // 3
+    nt = np.asarray(tracks["n_tracks"], np.int64)
+    ev = np.repeat(np.arange(E), nt)
+    slot = np.concatenate([base[e] + np.arange(nt[e]) for e in range(E)]) if E else np.zeros(0, np.int64)
+    slot = slot.astype(np.int64)
+    nh = np.asarray(tracks["nhits"])[slot].astype(np.int64)
+    hidx = np.asarray(tracks["hit_idx"]).reshape(-1, 26)[slot].astype(np.int64)
+    absidx = offsets[ev][:, None] + hidx
+    keys = np.asarray(hits["key"])[absidx]
+    mask = np.arange(26)[None, :] < nh[:, None]
+    keys = np.where(mask, keys, 0)
+    return ev, slot, nh, keys
+
+
+def match_tracks(truth: Truth, ev, nh, keys):
+    """Particle matched to each track by the 70 % rule (-1 = ghost)."""
+    T = len(ev)
+    if T == 0:
+        return np.zeros(0, np.int64)
+    mask = np.arange(26)[None, :] < nh[:, None]
+    pk = truth.hit_particle(np.repeat(ev, 26).reshape(T, 26), keys)
+    pk = np.where(mask, pk, -2)
+    out = np.full(T, -1, np.int64)
+    srt = np.sort(pk, axis=1)
+    # most frequent non-negative id per row
+    best_cnt = np.zeros(T, np.int64)
+    best_id = np.full(T, -1, np.int64)
+    run_id = srt[:, 0].copy()
+    run_cnt = np.ones(T, np.int64)
+    for j in range(1, 27):
+        cur = srt[:, j] if j < 26 else np.full(T, -3, np.int64)
+        same = cur == run_id
+        run_cnt = np.where(same, run_cnt + 1, run_cnt)
+        end = ~same
+        better = end & (run_id >= 0) & (run_cnt > best_cnt)
+        best_cnt = np.where(better, run_cnt, best_cnt)
+        best_id = np.where(better, run_id, best_id)
+        run_id = np.where(end, cur, run_id)
+        run_cnt = np.where(end, 1, run_cnt)
+    ok = best_cnt * 10 >= 7 * nh
+    out[ok] = best_id[ok]
+    return out
+
+
+def metrics(truth: Truth, ev, nh, keys, accepted) -> dict:
+    m = match_tracks(truth, ev, nh, keys)
+    acc = np.asarray(accepted, bool)
+    n_acc = int(acc.sum())
+    ghosts = int(np.count_nonzero(acc & (m < 0)))
+    matched = acc & (m >= 0)
+    pairs = np.unique((np.asarray(ev, np.int64)[matched] << 35) | m[matched])
+    reco = set(((truth.reco_ev[truth.reco_ok] << 35) | truth.reco_pid[truth.reco_ok]).tolist())
+    found = sum(1 for p in pairs.tolist() if p in reco)
+    n_m = int(matched.sum())
+    return dict(
+        n_tracks=n_acc, ghosts=ghosts, ghost_rate=ghosts / max(n_acc, 1),
+        efficiency=found / max(truth.n_reconstructible, 1),
+        n_reconstructible=truth.n_reconstructible, found=found,
+        clone_rate=(n_m - len(pairs)) / max(n_m, 1),
+    )
