@@ -1,0 +1,148 @@
+// fit.hip -- VELO track fit (paper Sec. 2.3.1, third and fourth paragraphs):
+// a simple Kalman filter per projection with x and y independent, process
+// noise from multiple scattering for a constant transverse momentum pt0,
+// then the transport to the point of closest approach to the beamline.
+//
+// One lane per track.  The hits are streamed in decreasing z (the order in
+// which track finding stores them), so the filter keeps only the previous
+// hit; both projections advance in the same loop.  The arithmetic is the
+// binary32 sequence below in this order (no contraction):
+//   init at hit 1 from hits 0, 1:  u = m1, t = (m1-m0)/d, d = z1-z0,
+//        C00 = s2, C01 = s2/d, C11 = (2 s2)/(d d)
+//   per hit i >= 2:  C11 += dl*ms2 (dl = planes crossed), u += t*dz,
+//        C00 += 2 dz C01 + dz dz C11, C01 += dz C11, r = m - u, S = C00 + s2,
+//        K0 = C00/S, K1 = C01/S, u += K0 r, t += K1 r, C11 -= K1 C01,
+//        C01 -= K0 C01, C00 -= K0 C00, chi2 += (r r)/S
+//   ms2 = (184.96 X/X0 / pt0^2) t2/(1+t2), t2 = squared slope of hits 0, 1
+//        (13.6 MeV Highland constant, p = pt0 sqrt(1+t2)/sqrt(t2))
+//   beamline: dzb = -(x tx + y ty)/(tx tx + ty ty) (0 if the slope is below
+//        1e-6), one plane of slope noise, then transport by dzb.
+#include "velo_device.hpp"
+
+namespace velo {
+
+struct FitConst {
+  float sig2;  // sigma_meas^2
+  float kms;   // 184.96 * x_over_x0 / pt0^2
+  float qc3, qc4;
+};
+
+struct Kf1 {
+  float u, t, c00, c01, c11, chi2;
+};
+
+__device__ __forceinline__ void kf_step(Kf1& s, float m, float dz, float dl, float ms2, float sig2) {
+  s.c11 = s.c11 + dl * ms2;
+  s.u = s.u + s.t * dz;
+  s.c00 = s.c00 + 2.0f * dz * s.c01 + dz * dz * s.c11;
+  s.c01 = s.c01 + dz * s.c11;
+  const float r = m - s.u;
+  const float S = s.c00 + sig2;
+  const float k0 = s.c00 / S;
+  const float k1 = s.c01 / S;
+  s.u = s.u + k0 * r;
+  s.t = s.t + k1 * r;
+  s.c11 = s.c11 - k1 * s.c01;
+  s.c01 = s.c01 - k0 * s.c01;
+  s.c00 = s.c00 - k0 * s.c00;
+  s.chi2 = s.chi2 + (r * r) / S;
+}
+
+__device__ __forceinline__ void kf_transport(Kf1& s, float dz) {
+  s.u = s.u + s.t * dz;
+  s.c00 = s.c00 + 2.0f * dz * s.c01 + dz * dz * s.c11;
+  s.c01 = s.c01 + dz * s.c11;
+}
+
+__global__ __launch_bounds__(64) void k_fit(const float* __restrict__ X, const float* __restrict__ Y,
+                                            const uint32_t* __restrict__ key,
+                                            const uint64_t* __restrict__ offsets, uint64_t n_pixels,
+                                            const uint32_t* __restrict__ n_tracks,
+                                            const uint8_t* __restrict__ nhits,
+                                            const uint32_t* __restrict__ hit_idx, FitConst P,
+                                            velo_states o) {
+  const uint32_t e = blockIdx.x;
+  const uint64_t b = offsets[e], end = offsets[e + 1];
+  if (end < b || end > n_pixels) return;
+  const uint32_t ne = (uint32_t)(end - b);
+  const uint64_t base = b / 3;
+  const uint32_t nt = n_tracks[e];
+  for (uint32_t t = threadIdx.x; t < nt; t += 64) {
+    const uint64_t slot = base + t;
+    const int n = nhits[slot];
+    const uint32_t* hi = hit_idx + 26ull * slot;
+    if (n < 3 || n > kLayers) continue;
+    uint32_t i0 = hi[0], i1 = hi[1];
+    if (i0 >= ne || i1 >= ne) continue;
+    const float x0 = X[b + i0], y0 = Y[b + i0], x1 = X[b + i1], y1 = Y[b + i1];
+    const uint32_t l0 = key[b + i0] >> 22, l1 = key[b + i1] >> 22;
+    const float z0 = kLayerZ[l0 < 26u ? l0 : 25u], z1 = kLayerZ[l1 < 26u ? l1 : 25u];
+    const float d = z1 - z0;
+    const float tx0 = (x1 - x0) / d;
+    const float ty0 = (y1 - y0) / d;
+    const float t2 = tx0 * tx0 + ty0 * ty0;
+    const float ms2 = (P.kms * t2) / (1.0f + t2);
+    const float s2 = P.sig2;
+    Kf1 sx{x1, tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+    Kf1 sy{y1, ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+    float zp = z1;
+    uint32_t lp = l1;
+    bool ok = true;
+    for (int j = 2; j < n; ++j) {
+      const uint32_t ij = hi[j];
+      if (ij >= ne) { ok = false; break; }
+      const uint32_t lj = key[b + ij] >> 22;
+      const float zj = kLayerZ[lj < 26u ? lj : 25u];
+      const float dz = zj - zp;
+      const float dl = (float)((int)lp - (int)lj);
+      kf_step(sx, X[b + ij], dz, dl, ms2, s2);
+      kf_step(sy, Y[b + ij], dz, dl, ms2, s2);
+      zp = zj;
+      lp = lj;
+    }
+    if (!ok) continue;
+    const float num = sx.u * sx.t + sy.u * sy.t;
+    const float den = sx.t * sx.t + sy.t * sy.t;
+    const float dzb = den < 1e-12f ? 0.0f : -(num / den);
+    sx.c11 = sx.c11 + ms2;
+    sy.c11 = sy.c11 + ms2;
+    kf_transport(sx, dzb);
+    kf_transport(sy, dzb);
+    const float chi2 = sx.chi2 + sy.chi2;
+    const int ndof = 2 * n - 4;
+    o.x[slot] = sx.u;
+    o.y[slot] = sy.u;
+    o.z[slot] = zp + dzb;
+    o.tx[slot] = sx.t;
+    o.ty[slot] = sy.t;
+    o.cov_x[3 * slot] = sx.c00;
+    o.cov_x[3 * slot + 1] = sx.c01;
+    o.cov_x[3 * slot + 2] = sx.c11;
+    o.cov_y[3 * slot] = sy.c00;
+    o.cov_y[3 * slot + 1] = sy.c01;
+    o.cov_y[3 * slot + 2] = sy.c11;
+    o.chi2[slot] = chi2;
+    o.ndof[slot] = ndof;
+    const float r = chi2 / (float)ndof;
+    o.accepted[slot] = (uint8_t)(n >= 4 ? (r <= P.qc4) : (r <= P.qc3));
+  }
+}
+
+FitConst make_fit_const(const velo_params* p) {
+  FitConst c;
+  c.sig2 = p->sigma_meas * p->sigma_meas;
+  c.kms = (184.96f * p->x_over_x0) / (p->pt0_mev * p->pt0_mev);
+  c.qc3 = p->qc3;
+  c.qc4 = p->qc4;
+  return c;
+}
+
+hipError_t launch_fit(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
+                      uint32_t n_events, uint64_t n_pixels, const velo_params* p,
+                      const velo_states* o, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit, dim3(n_events), dim3(64), 0, s, h->x, h->y, h->key, offsets, n_pixels,
+                     t->n_tracks, t->nhits, t->hit_idx, make_fit_const(p), *o);
+  return hipGetLastError();
+}
+
+}  // namespace velo

@@ -1,0 +1,79 @@
+// velo_device.hpp -- device-side constants and helpers shared by the HIP
+// kernels of libvelo (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/velo.h"
+
+namespace velo {
+
+constexpr int kLayers = 26;
+constexpr int kPix = 1536;
+constexpr int kWave = 64;
+
+// Plane positions: -280 mm + 1030 mm * l / 25, evaluated in double and
+// rounded once to binary32 (constant-folded at compile time).
+#define VELO_Z(l) ((float)(-280.0 + 1030.0 * (double)(l) / 25.0))
+__constant__ const float kLayerZ[kLayers] = {
+    VELO_Z(0),  VELO_Z(1),  VELO_Z(2),  VELO_Z(3),  VELO_Z(4),  VELO_Z(5),  VELO_Z(6),
+    VELO_Z(7),  VELO_Z(8),  VELO_Z(9),  VELO_Z(10), VELO_Z(11), VELO_Z(12), VELO_Z(13),
+    VELO_Z(14), VELO_Z(15), VELO_Z(16), VELO_Z(17), VELO_Z(18), VELO_Z(19), VELO_Z(20),
+    VELO_Z(21), VELO_Z(22), VELO_Z(23), VELO_Z(24), VELO_Z(25)};
+#undef VELO_Z
+
+// raw word fields
+__device__ __forceinline__ uint32_t w_col(uint32_t w) { return w & 0x7FFu; }
+__device__ __forceinline__ uint32_t w_row(uint32_t w) { return (w >> 11) & 0x7FFu; }
+__device__ __forceinline__ uint32_t w_layer(uint32_t w) { return (w >> 22) & 31u; }
+__device__ __forceinline__ uint32_t w_charge(uint32_t w) { return (w >> 27) & 15u; }
+
+// inactive pixel: centre radius < 5.1 mm, in exact integer form
+__device__ __forceinline__ bool in_hole(uint32_t col, uint32_t row) {
+  int dc = 2 * (int)col - 1535, dr = 2 * (int)row - 1535;
+  return dc * dc + dr * dr <= 34393;
+}
+
+// exclusive prefix count of `pred` over the 64 lanes of the calling wave;
+// *total receives the wave's count
+__device__ __forceinline__ uint32_t wave_prefix(bool pred, uint32_t* total) {
+  uint64_t m = __ballot(pred);
+  *total = (uint32_t)__popcll(m);
+  uint32_t lo = __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u);
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), lo);
+}
+
+// Workgroup exclusive scan of one value per thread; NT threads, `tmp` holds
+// NT/64 + 1 uint32 of LDS.  Returns the exclusive prefix; *total = sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  // inclusive wave scan
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if constexpr (NW == 1) {
+    *total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+  } else {
+    if (lane == kWave - 1) tmp[wid] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      uint32_t t = tmp[w];
+      if (w < wid) base += t;
+      tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+  }
+}
+
+}  // namespace velo
