@@ -202,47 +202,54 @@ __device__ __forceinline__ uint32_t event_of(const uint64_t* __restrict__ offset
   return lo;
 }
 
+constexpr uint32_t kValWords = 16;  // words per thread of k_validate
+
 __global__ __launch_bounds__(256) void k_validate(const uint32_t* __restrict__ px,
                                                   const uint64_t* __restrict__ offsets,
                                                   uint32_t n_events, uint64_t n_pixels,
                                                   uint32_t* __restrict__ status,
                                                   uint32_t* __restrict__ layer_start) {
   __shared__ uint32_t ev_range[2];
-  const uint64_t i0 = (uint64_t)blockIdx.x * 256;
-  const uint64_t i = i0 + threadIdx.x;
+  const uint64_t span = 256ull * kValWords;
+  const uint64_t i0 = (uint64_t)blockIdx.x * span;
   if (threadIdx.x < 2) {
-    uint64_t probe = threadIdx.x == 0 ? i0 : (i0 + 255 < n_pixels ? i0 + 255 : n_pixels - 1);
+    const uint64_t last = i0 + span - 1 < n_pixels ? i0 + span - 1 : n_pixels - 1;
+    const uint64_t probe = threadIdx.x == 0 ? i0 : last;
     uint32_t e = 0;
     if (offsets[0] <= probe) e = event_of(offsets, 0, n_events - 1, probe);
     ev_range[threadIdx.x] = e;
   }
   __syncthreads();
-  if (i >= n_pixels || offsets[0] > i) return;
   uint32_t lo = ev_range[0], hi = ev_range[1];
   if (hi < lo) hi = lo;  // offsets not monotone: the event is flagged by k_finalize
-  uint32_t e = event_of(offsets, lo, hi, i);
-  const uint64_t b = offsets[e], end = offsets[e + 1];
-  if (!(b <= i && i < end) || end > n_pixels) return;
-  const uint32_t w = px[i];
-  const uint32_t p = (uint32_t)(i - b), n = (uint32_t)(end - b);
-  const uint32_t col = w_col(w), row = w_row(w), lay = w_layer(w), q = w_charge(w);
-  uint32_t flags = 0;
-  const bool valid = !(w >> 31) && lay < (uint32_t)kLayers && row < (uint32_t)kPix &&
-                     col < (uint32_t)kPix && q >= 1u;
-  if (!valid) flags |= VELO_EV_BAD_WORD;
-  else if (in_hole(col, row)) flags |= VELO_EV_HOLE;
-  const uint32_t lc = lay < 26u ? lay : 26u;
-  int lp = -1;
-  if (p > 0) {
-    const uint32_t wp = w_layer(px[i - 1]);
-    if (lay < wp) flags |= VELO_EV_LAYER_ORDER;
-    lp = (int)(wp < 26u ? wp : 26u);
+#pragma unroll 4
+  for (uint32_t k = 0; k < kValWords; ++k) {
+    const uint64_t i = i0 + threadIdx.x + 256ull * k;
+    if (i >= n_pixels || offsets[0] > i) continue;
+    const uint32_t e = event_of(offsets, lo, hi, i);
+    const uint64_t b = offsets[e], end = offsets[e + 1];
+    if (!(b <= i && i < end) || end > n_pixels) continue;
+    const uint32_t w = px[i];
+    const uint32_t p = (uint32_t)(i - b), n = (uint32_t)(end - b);
+    const uint32_t col = w_col(w), row = w_row(w), lay = w_layer(w), q = w_charge(w);
+    uint32_t flags = 0;
+    const bool valid = !(w >> 31) && lay < (uint32_t)kLayers && row < (uint32_t)kPix &&
+                       col < (uint32_t)kPix && q >= 1u;
+    if (!valid) flags |= VELO_EV_BAD_WORD;
+    else if (in_hole(col, row)) flags |= VELO_EV_HOLE;
+    const uint32_t lc = lay < 26u ? lay : 26u;
+    int lp = -1;
+    if (p > 0) {
+      const uint32_t wp = w_layer(px[i - 1]);
+      if (lay < wp) flags |= VELO_EV_LAYER_ORDER;
+      lp = (int)(wp < 26u ? wp : 26u);
+    }
+    if (flags) atomicOr(status + e, flags);
+    uint32_t* ls = layer_start + 27ull * e;
+    for (int l = lp + 1; l <= (int)lc; ++l) ls[l] = p;
+    if (p == n - 1)
+      for (int l = (int)lc + 1; l <= 26; ++l) ls[l] = n;
   }
-  if (flags) atomicOr(status + e, flags);
-  uint32_t* ls = layer_start + 27ull * e;
-  for (int l = lp + 1; l <= (int)lc; ++l) ls[l] = p;
-  if (p == n - 1)
-    for (int l = (int)lc + 1; l <= 26; ++l) ls[l] = n;
 }
 
 // offsets of event e are usable (monotone and inside the buffer)
@@ -360,7 +367,8 @@ hipError_t launch_cluster(const uint32_t* px, const uint64_t* offsets, uint32_t 
   hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
                      mid_count);
   if (n_pixels > 0)
-    hipLaunchKernelGGL(k_validate, dim3((unsigned)((n_pixels + 255) / 256)), dim3(256), 0, s, px,
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
+                       dim3(256), 0, s, px,
                        offsets, n_events, n_pixels, h->status, h->layer_start);
   hipLaunchKernelGGL(k_small, dim3(n_events * kLayers), dim3(64), 0, s, px, offsets, n_pixels,
                      h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list);

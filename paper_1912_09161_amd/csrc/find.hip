@@ -3,12 +3,13 @@
 // planes, extended to the other planes along straight lines; hits of every
 // plane kept in azimuth order for fast look-up).
 //
-// One workgroup per event walks the planes from z = +750 mm down.  The three
-// planes in use (l+2, l+1, l) are staged in a ring of per-plane tables:
-// coordinates, a counting sort of the hits into azimuth buckets (a monotone
-// pseudo-angle of x, y), used flags.  Candidate windows in pseudo-angle are
-// derived conservatively from the exact cuts, so they only accelerate; every
-// decision uses the exact binary32 cut expressions.
+// k_phi_tables first sorts the hits of every (event, plane) into kNB azimuth
+// buckets of a monotone pseudo-angle of (x, y) (one wave per plane, counting
+// sort).  Then one workgroup per event walks the planes from z = +750 mm
+// down; the three planes in use (l+2, l+1, l) are staged in a ring of LDS
+// tables: coordinates, bucket order, used flags.  Candidate windows in
+// pseudo-angle are derived conservatively from the exact cuts, so they only
+// accelerate; every decision uses the exact binary32 cut expressions.
 //
 // Conflicts are resolved exactly like the sequential greedy rule (ascending
 // priority, a candidate wins iff none of its hits / its track is taken):
@@ -21,10 +22,11 @@
 // slots, hit lists and counts are written directly; no atomics decide an
 // output position.
 //
-// Three tiers share one implementation: 64 lanes with small LDS tables, 256
-// lanes with large LDS tables, and 256 lanes with tables in the caller's
-// workspace at the event's own hit / track positions.  An event whose tables
-// outgrow its tier is re-run from scratch by the next tier.
+// Three tiers share one implementation: one wave with small LDS tables, 256
+// lanes with large LDS tables, and 256 lanes reading the bucket tables in
+// place with per-event scratch in the caller's workspace at the event's own
+// hit / track positions.  An event whose tables outgrow its tier is re-run
+// from scratch by the next tier.
 #include "velo_device.hpp"
 
 namespace velo {
@@ -38,15 +40,16 @@ struct FindConst {
   float rho_seed, rho_fwd;  // upper bounds of sqrt(s_seed), sqrt(s_fwd)
 };
 
+constexpr uint32_t kNB = 64;  // azimuth buckets per plane
+
 template <typename IDX>
 struct LayerTab {
-  float* hx;        // [cap] by local index (= rank of the hit's key in its plane)
-  float* hy;
-  IDX* bl;          // [cap] local indices in bucket order
-  uint8_t* used;    // [cap] by local index
-  uint32_t* best;   // [cap] by local index: candidate holding the hit in a round
-  uint32_t* bstart; // [B+1]
-  uint32_t* bcur;   // [B]
+  const float* hx;        // by local index (= rank of the hit's key in its plane)
+  const float* hy;
+  const IDX* bl;          // local indices in bucket order
+  uint8_t* used;          // by local index
+  uint32_t* best;         // by local index: candidate holding the hit in a round
+  const uint32_t* bstart; // [kNB + 1] first position of every bucket
 };
 
 struct TrackTab {
@@ -68,12 +71,56 @@ struct Cand {
   uint32_t a, b, c;  // extension: track, hit; seed: h0, h1, h2 (local indices)
 };
 
-template <typename IDX>
+struct Dbl {
+  uint32_t i01;  // h0 | h1 << 16 (local indices)
+  float tx, ty;
+};
+
+struct EventIO {
+  const float* X;          // hits of the event (absolute base applied)
+  const float* Y;
+  const uint32_t* lstart;  // [27]
+  const uint32_t* lnh;     // [26]
+  const uint32_t* order;   // bucket order of every plane (at the hits' slots)
+  const uint32_t* bst;     // [26 * (kNB + 1)] bucket starts of every plane
+  uint8_t* nhits;          // track outputs (absolute slots)
+  uint32_t* hit_idx;
+  uint64_t slot_base;
+};
+
+// Tables of one event.  RING (LDS tiers): the three planes in use are copied
+// into a ring of tables stored back to back (stride capL), addressed
+// arithmetically so that the pointers stay in registers.  !RING (workspace
+// tier): coordinates and bucket tables are read in place, used / best live
+// in scratch at the hits' own event-relative slots.
+template <typename IDX, bool RING>
 struct FindMem {
-  LayerTab<IDX> L[3];
+  float* hx;
+  float* hy;
+  IDX* bl;
+  uint8_t* used;
+  uint32_t* best;
+  uint32_t* bstart;  // [3 * (kNB + 1)]
   TrackTab T;
   Cand* cand;
-  uint32_t capL, capT, capC, nb;  // capacities, number of azimuth buckets
+  // seed doublet search (LDS tiers): per middle hit the two bucket ranges of
+  // its window on plane l+2 (start | length << 16) and the prefix of their
+  // lengths; passing doublets
+  uint32_t* w0;
+  uint32_t* w1;
+  uint32_t* wp;   // [capL + 1]
+  Dbl* dbl;       // [capD]
+  uint32_t capL, capT, capC, capD;
+  __device__ __forceinline__ LayerTab<IDX> layer(const EventIO& io, int l) const {
+    if constexpr (RING) {
+      const uint32_t r = (uint32_t)l % 3u, o = r * capL;
+      return LayerTab<IDX>{hx + o, hy + o, bl + o, used + o, best + o, bstart + r * (kNB + 1)};
+    } else {
+      const uint32_t o = io.lstart[l];
+      return LayerTab<IDX>{io.X + o, io.Y + o, io.order + o, used + o, best + o,
+                           io.bst + (uint32_t)l * (kNB + 1)};
+    }
+  }
 };
 
 // Monotone pseudo-angle of (x, y) in [0, 4]; its derivative with respect to
@@ -136,61 +183,70 @@ __device__ __forceinline__ uint32_t lda(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct EventIO {
-  const float* X;          // hits of the event (absolute base applied)
-  const float* Y;
-  const uint32_t* lstart;  // [27]
-  const uint32_t* lnh;     // [26]
-  uint8_t* nhits;          // track outputs at the event's slot base
-  uint32_t* hit_idx;
-  uint64_t slot_base;
-};
-
 // shared scalars of one event
 struct FindScal {
   uint32_t nc;       // candidates found this step (may exceed capC)
+  uint32_t nd;       // seed doublets found this step (may exceed capD)
   uint32_t flag;     // any live candidate left
   uint32_t n_act;    // active tracks
   uint32_t n_created;
   uint32_t fail;     // 0 ok, 1 escalate, 2 overflow
   uint32_t tmp[8];   // scan scratch (NT/64 + 1)
+  uint32_t lstart[27], lnh[26];  // plane tables of the event
+  float z[kLayers];              // plane positions
 };
 
-// Load plane l into ring table `t`: coordinates, bucket counting sort.
-template <int NT, typename IDX>
-__device__ void load_plane(const EventIO& io, int l, LayerTab<IDX>& t, uint32_t nb, FindScal& sc) {
-  const uint32_t n = io.lnh[l], base = io.lstart[l];
-  for (uint32_t b = threadIdx.x; b < nb; b += NT) t.bcur[b] = 0;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += NT) {
-    float x = io.X[base + i], y = io.Y[base + i];
-    t.hx[i] = x;
-    t.hy[i] = y;
-    t.used[i] = 0;
-    uint32_t b = bucket_of(pangle(x, y), nb);
-    t.best[i] = b;
-    atomicAdd(t.bcur + b, 1u);
+// Staging of plane l.  RING tiers: the coordinates, bucket order and bucket
+// starts of the next plane are loaded into registers one step ahead (issue)
+// and stored into the ring table at the start of its step (commit), so the
+// global-memory latency overlaps a whole step.  Used flags are cleared at
+// commit.  Workspace tier: only the used flags are cleared.
+template <int NT, typename IDX, bool RING>
+struct PlanePrefetch {
+  static constexpr int PF = RING ? 4 : 1;            // hits per lane (capL <= 4 NT)
+  static constexpr int PB = (kNB + 1 + NT - 1) / NT;  // bucket starts per lane
+  float x[PF], y[PF];
+  uint32_t o[PF], bs[PB];
+  __device__ __forceinline__ void issue(const EventIO& io, int l, uint32_t capL) {
+    if constexpr (RING) {
+      const uint32_t n = io.lnh[l], base = io.lstart[l];
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < n && i < capL) { x[k] = io.X[base + i]; y[k] = io.Y[base + i]; o[k] = io.order[base + i]; }
+      }
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        const uint32_t b = threadIdx.x + k * NT;
+        if (b <= kNB) bs[k] = io.bst[(uint32_t)l * (kNB + 1) + b];
+      }
+    }
   }
-  __syncthreads();
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += NT) {
-    uint32_t b = b0 + threadIdx.x;
-    uint32_t c = b < nb ? lda(t.bcur + b) : 0u;
-    uint32_t tot;
-    uint32_t ex = block_scan<NT>(c, sc.tmp, &tot);
-    __syncthreads();
-    if (b < nb) { t.bstart[b] = carry + ex; t.bcur[b] = carry + ex; }
-    carry += tot;
+  template <typename MEM>
+  __device__ __forceinline__ void commit(const EventIO& io, int l, const MEM& M) {
+    const uint32_t n = io.lnh[l];
+    const LayerTab<IDX> t = M.layer(io, l);
+    if constexpr (RING) {
+      float* hx = const_cast<float*>(t.hx);
+      float* hy = const_cast<float*>(t.hy);
+      IDX* bl = const_cast<IDX*>(t.bl);
+      uint32_t* bsd = const_cast<uint32_t*>(t.bstart);
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; bl[i] = (IDX)o[k]; t.used[i] = 0; }
+      }
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        const uint32_t b = threadIdx.x + k * NT;
+        if (b <= kNB) bsd[b] = bs[k];
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < n; i += NT) t.used[i] = 0;
+    }
+    wg_barrier<RING>();
   }
-  if (threadIdx.x == 0) t.bstart[nb] = carry;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += NT) {
-    uint32_t b = t.best[i];
-    uint32_t pos = atomicAdd(t.bcur + b, 1u);
-    t.bl[pos] = (IDX)i;
-  }
-  __syncthreads();
-}
+};
 
 template <typename IDX, typename F>
 __device__ __forceinline__ void scan_window(const LayerTab<IDX>& t, Ranges r, F f) {
@@ -200,32 +256,37 @@ __device__ __forceinline__ void scan_window(const LayerTab<IDX>& t, Ranges r, F 
 }
 
 // Returns 0 when done, 1 when the event needs a larger tier, 2 on overflow.
-template <int NT, typename IDX>
-__device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<IDX>& M, FindScal& sc) {
+template <int NT, typename IDX, bool RING>
+__device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindConst& P,
+                                               const FindMem<IDX, RING>& M, FindScal& sc) {
   const uint32_t tid = threadIdx.x;
+  const float* zt = sc.z;
   for (int l = 0; l < kLayers; ++l)
     if (io.lnh[l] > M.capL) return 1u;
   if (tid == 0) { sc.n_act = 0; sc.n_created = 0; sc.fail = 0; }
-  __syncthreads();
-  TrackTab& A = M.T;
+  PlanePrefetch<NT, IDX, RING> pf;
+  pf.issue(io, kLayers - 1, M.capL);
+  wg_barrier<RING>();
+  const TrackTab A = M.T;
   for (int l = kLayers - 1; l >= 0; --l) {
-    LayerTab<IDX>& T0 = M.L[l % 3];
-    load_plane<NT>(io, l, T0, M.nb, sc);
+    pf.commit(io, l, M);
+    if (l > 0) pf.issue(io, l - 1, M.capL);
+    const LayerTab<IDX> T0 = M.layer(io, l);
     const uint32_t n0 = io.lnh[l], base0 = io.lstart[l];
-    const float zl = kLayerZ[l];
+    const float zl = zt[l];
     const uint32_t n_act = sc.n_act;
 
     // ---- 1. extend active tracks into plane l ----
     if (tid == 0) sc.nc = 0;
     for (uint32_t t = tid; t < n_act; t += NT) { A.tmatch[t] = kNone; }
-    __syncthreads();
+    wg_barrier<RING>();
     for (uint32_t t = tid; t < n_act; t += NT) {
       const float xa = A.xa[t], ya = A.ya[t], txf = A.tx[t], tyf = A.ty[t];
-      const float za = kLayerZ[A.la[t]];
+      const float za = zt[A.la[t]];
       const float d = zl - za;
       const float xp = xa + txf * d;
       const float yp = ya + tyf * d;
-      Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), M.nb);
+      Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
       scan_window(T0, r, [&](uint32_t h) {
         float dx = T0.hx[h] - xp, dy = T0.hy[h] - yp;
         float s = dx * dx + dy * dy;
@@ -235,7 +296,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         }
       });
     }
-    __syncthreads();
+    wg_barrier<RING>();
     {
       const uint32_t nc = sc.nc;
       if (nc > VELO_MAX_CANDIDATES) return 2u;
@@ -256,7 +317,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         for (uint32_t h = tid; h < n0; h += NT) T0.best[h] = kNone;
         for (uint32_t t = tid; t < n_act; t += NT) A.tbest[t] = kNone;
         if (tid == 0) sc.flag = 0;
-        __syncthreads();
+        wg_barrier<RING>();
         for (uint32_t k = tid; k < nc; k += NT) {
           const Cand c = M.cand[k];
           if (A.tmatch[c.a] == kNone && !T0.used[c.b]) {
@@ -264,7 +325,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
             cas_min(A.tbest + c.a, k, less_trk);
           }
         }
-        __syncthreads();
+        wg_barrier<RING>();
         for (uint32_t k = tid; k < nc; k += NT) {
           const Cand c = M.cand[k];
           if (A.tmatch[c.a] == kNone && !T0.used[c.b] && lda(T0.best + c.b) == k &&
@@ -273,16 +334,16 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
             T0.used[c.b] = 1;
           }
         }
-        __syncthreads();
+        wg_barrier<RING>();
         bool live = false;
         for (uint32_t k = tid; k < nc; k += NT) {
           const Cand c = M.cand[k];
           if (A.tmatch[c.a] == kNone && !T0.used[c.b]) live = true;
         }
         if (live) sc.flag = 1;
-        __syncthreads();
+        wg_barrier<RING>();
         if (!sc.flag) break;
-        __syncthreads();
+        wg_barrier<RING>();
       }
     }
     // apply: append matched hits, count misses
@@ -292,7 +353,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         const uint32_t nn = A.n[t];
         io.hit_idx[26ull * A.slot[t] + nn] = base0 + h;
         const float xh = T0.hx[h], yh = T0.hy[h];
-        const float dz = zl - kLayerZ[A.la[t]];
+        const float dz = zl - zt[A.la[t]];
         A.tx[t] = (xh - A.xa[t]) / dz;
         A.ty[t] = (yh - A.ya[t]) / dz;
         A.xa[t] = xh;
@@ -306,51 +367,113 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         if (sk > P.max_skip) io.nhits[A.slot[t]] = A.n[t];
       }
     }
-    __syncthreads();
+    wg_barrier<RING>();
 
     // ---- 2. seeds on planes (l+2, l+1, l) ----
     uint32_t n_new = 0;
-    LayerTab<IDX>& T1 = M.L[(l + 1) % 3];
-    LayerTab<IDX>& T2 = M.L[(l + 2) % 3];
+    const LayerTab<IDX> T1 = M.layer(io, l < kLayers - 1 ? l + 1 : l);
+    const LayerTab<IDX> T2 = M.layer(io, l < kLayers - 2 ? l + 2 : l);
     uint32_t n1 = 0, n2 = 0;
     if (l <= kLayers - 3) {
       n1 = io.lnh[l + 1];
       n2 = io.lnh[l + 2];
-      const float z0 = kLayerZ[l + 2], z1 = kLayerZ[l + 1], z2 = zl;
-      if (tid == 0) sc.nc = 0;
-      __syncthreads();
-      for (uint32_t i1 = tid; i1 < n1; i1 += NT) {
-        if (T1.used[i1]) continue;
-        const float x1 = T1.hx[i1], y1 = T1.hy[i1];
-        Ranges r0 = window(pangle(x1, y1), P.win_doublet, M.nb);
-        scan_window(T2, r0, [&](uint32_t i0) {
-          if (T2.used[i0]) return;
-          const float x0 = T2.hx[i0], y0 = T2.hy[i0];
-          const float dz = z1 - z0;
-          const float tx = (x1 - x0) / dz;
-          const float ty = (y1 - y0) / dz;
-          if (!(fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t)) return;
-          const float cr = x0 * y1 - y0 * x1;
-          const float r0s = x0 * x0 + y0 * y0;
-          const float r1s = x1 * x1 + y1 * y1;
-          if (!(cr * cr <= (P.sin2 * r0s) * r1s)) return;
-          if (!(x0 * x1 + y0 * y1 > 0.0f)) return;
-          const float d = z2 - z1;
-          const float xp = x1 + tx * d;
-          const float yp = y1 + ty * d;
-          Ranges r2 = window(pangle(xp, yp), point_window(xp, yp, P.rho_seed), M.nb);
-          scan_window(T0, r2, [&](uint32_t i2) {
-            if (T0.used[i2]) return;
-            const float dx = T0.hx[i2] - xp, dy = T0.hy[i2] - yp;
-            const float s = dx * dx + dy * dy;
-            if (s <= P.s_seed) {
-              uint32_t k = atomicAdd(&sc.nc, 1u);
-              if (k < M.capC) M.cand[k] = Cand{s, i0, i1, i2};
-            }
-          });
+      const float z0 = zt[l + 2], z1 = zt[l + 1], z2 = zl;
+      if (tid == 0) { sc.nc = 0; sc.nd = 0; }
+      wg_barrier<RING>();
+      const float dz01 = z1 - z0;
+      const float d12 = z2 - z1;
+      // third hit of a doublet (h0, h1): unused, within sqrt(s_seed) of the line
+      auto triplets = [&](uint32_t i0, uint32_t i1, float tx, float ty) {
+        const float xp = T1.hx[i1] + tx * d12;
+        const float yp = T1.hy[i1] + ty * d12;
+        Ranges r2 = window(pangle(xp, yp), point_window(xp, yp, P.rho_seed), kNB);
+        scan_window(T0, r2, [&](uint32_t i2) {
+          if (T0.used[i2]) return;
+          const float dx = T0.hx[i2] - xp, dy = T0.hy[i2] - yp;
+          const float s = dx * dx + dy * dy;
+          if (s <= P.s_seed) {
+            uint32_t k = atomicAdd(&sc.nc, 1u);
+            if (k < M.capC) M.cand[k] = Cand{s, i0, i1, i2};
+          }
         });
+      };
+      // doublet cuts of (h0 on l+2, h1 on l+1); returns false if rejected
+      auto doublet = [&](uint32_t i0, uint32_t i1, float& tx, float& ty) {
+        const float x0 = T2.hx[i0], y0 = T2.hy[i0], x1 = T1.hx[i1], y1 = T1.hy[i1];
+        tx = (x1 - x0) / dz01;
+        ty = (y1 - y0) / dz01;
+        if (!(fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t)) return false;
+        const float cr = x0 * y1 - y0 * x1;
+        const float r0s = x0 * x0 + y0 * y0;
+        const float r1s = x1 * x1 + y1 * y1;
+        if (!(cr * cr <= (P.sin2 * r0s) * r1s)) return false;
+        return x0 * x1 + y0 * y1 > 0.0f;
+      };
+      if constexpr (RING) {
+        // (a) window of every unused middle hit on plane l+2, prefix of the sizes
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < n1; b0 += NT) {
+          const uint32_t i1 = b0 + tid;
+          uint32_t cnt = 0;
+          if (i1 < n1 && !T1.used[i1]) {
+            const Ranges r = window(pangle(T1.hx[i1], T1.hy[i1]), P.win_doublet, kNB);
+            const uint32_t s0 = T2.bstart[r.b0], l0 = T2.bstart[r.b1 + 1] - s0;
+            uint32_t s1 = 0, l1 = 0;
+            if (r.b2 <= r.b3) { s1 = T2.bstart[r.b2]; l1 = T2.bstart[r.b3 + 1] - s1; }
+            M.w0[i1] = s0 | (l0 << 16);
+            M.w1[i1] = s1 | (l1 << 16);
+            cnt = l0 + l1;
+          }
+          uint32_t tot;
+          const uint32_t ex = block_scan<NT, RING>(cnt, sc.tmp, &tot);
+          if (i1 < n1) M.wp[i1] = carry + ex;
+          carry += tot;
+        }
+        if (tid == 0) M.wp[n1] = carry;
+        wg_barrier<RING>();
+        // (b) all (h1, h0) pairs, split evenly over the lanes in contiguous chunks
+        const uint32_t total = carry, per = (total + NT - 1) / NT;
+        uint32_t j = tid * per;
+        const uint32_t jend = j + per < total ? j + per : total;
+        if (j < jend) {
+          uint32_t lo = 0, hi = n1 - 1;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (M.wp[mid] <= j) lo = mid; else hi = mid - 1;
+          }
+          uint32_t i1 = lo;
+          for (; j < jend; ++j) {
+            while (M.wp[i1 + 1] <= j) ++i1;
+            const uint32_t k = j - M.wp[i1], w0 = M.w0[i1], l0 = w0 >> 16;
+            const uint32_t p = k < l0 ? (w0 & 0xFFFFu) + k : (M.w1[i1] & 0xFFFFu) + (k - l0);
+            const uint32_t i0 = T2.bl[p];
+            if (T2.used[i0]) continue;
+            float tx, ty;
+            if (!doublet(i0, i1, tx, ty)) continue;
+            const uint32_t d = atomicAdd(&sc.nd, 1u);
+            if (d < M.capD) M.dbl[d] = Dbl{i0 | (i1 << 16), tx, ty};
+          }
+        }
+        wg_barrier<RING>();
+        const uint32_t nd = sc.nd;
+        if (nd > M.capD) return 1u;
+        // (c) third hits, one doublet per lane
+        for (uint32_t d = tid; d < nd; d += NT) {
+          const Dbl r = M.dbl[d];
+          triplets(r.i01 & 0xFFFFu, r.i01 >> 16, r.tx, r.ty);
+        }
+      } else {
+        for (uint32_t i1 = tid; i1 < n1; i1 += NT) {
+          if (T1.used[i1]) continue;
+          const Ranges r0 = window(pangle(T1.hx[i1], T1.hy[i1]), P.win_doublet, kNB);
+          scan_window(T2, r0, [&](uint32_t i0) {
+            if (T2.used[i0]) return;
+            float tx, ty;
+            if (doublet(i0, i1, tx, ty)) triplets(i0, i1, tx, ty);
+          });
+        }
       }
-      __syncthreads();
+      wg_barrier<RING>();
       const uint32_t nc = sc.nc;
       if (nc > VELO_MAX_CANDIDATES) return 2u;
       if (nc > M.capC) return 1u;
@@ -368,7 +491,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         for (uint32_t h = tid; h < n1; h += NT) T1.best[h] = kNone;
         for (uint32_t h = tid; h < n0; h += NT) T0.best[h] = kNone;
         if (tid == 0) sc.flag = 0;
-        __syncthreads();
+        wg_barrier<RING>();
         for (uint32_t k = tid; k < nc; k += NT) {
           const Cand c = M.cand[k];
           if (alive(c)) {
@@ -377,7 +500,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
             cas_min(T0.best + c.c, k, less_seed);
           }
         }
-        __syncthreads();
+        wg_barrier<RING>();
         for (uint32_t k = tid; k < nc; k += NT) {
           const Cand c = M.cand[k];
           if (alive(c) && lda(T2.best + c.a) == k && lda(T1.best + c.b) == k &&
@@ -388,21 +511,21 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
             M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
           }
         }
-        __syncthreads();
+        wg_barrier<RING>();
         bool live = false;
         for (uint32_t k = tid; k < nc; k += NT)
           if (alive(M.cand[k])) live = true;
         if (live) sc.flag = 1;
-        __syncthreads();
+        wg_barrier<RING>();
         if (!sc.flag) break;
-        __syncthreads();
+        wg_barrier<RING>();
       }
       // accepted seed of each h0 (its candidate index)
       for (uint32_t h = tid; h < n2; h += NT) T2.best[h] = kNone;
-      __syncthreads();
+      wg_barrier<RING>();
       for (uint32_t k = tid; k < nc; k += NT)
         if (M.cand[k].s < 0.0f) T2.best[M.cand[k].a] = k;
-      __syncthreads();
+      wg_barrier<RING>();
     }
 
     // ---- 3. active table: surviving tracks compacted in place, then new seeds ----
@@ -418,14 +541,14 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         f_tx = A.tx[t]; f_ty = A.ty[t]; f_la = A.la[t]; f_n = A.n[t]; f_skip = A.skip[t];
       }
       uint32_t tot;
-      const uint32_t pos = carry + block_scan<NT>(keep ? 1u : 0u, sc.tmp, &tot);
-      __syncthreads();  // every entry of this chunk is read before any is overwritten
+      const uint32_t pos = carry + block_scan<NT, RING>(keep ? 1u : 0u, sc.tmp, &tot);
+      wg_barrier<RING>();  // every entry of this chunk is read before any is overwritten
       if (keep) {
         A.slot[pos] = f_slot; A.key0[pos] = f_key0; A.xa[pos] = f_xa; A.ya[pos] = f_ya;
         A.tx[pos] = f_tx; A.ty[pos] = f_ty; A.la[pos] = f_la; A.n[pos] = f_n; A.skip[pos] = f_skip;
       }
       carry += tot;
-      __syncthreads();
+      wg_barrier<RING>();
     }
     const uint32_t n_keep = carry;
     if (l <= kLayers - 3) {
@@ -436,7 +559,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
         const uint32_t i0 = b0 + tid < n2 ? n2 - 1 - (b0 + tid) : kNone;
         const uint32_t k = i0 != kNone ? lda(T2.best + i0) : kNone;
         uint32_t tot;
-        const uint32_t rank = c2 + block_scan<NT>(k != kNone ? 1u : 0u, sc.tmp, &tot);
+        const uint32_t rank = c2 + block_scan<NT, RING>(k != kNone ? 1u : 0u, sc.tmp, &tot);
         if (k != kNone) {
           const Cand c = M.cand[k];
           const uint32_t slot = (uint32_t)io.slot_base + created + rank;
@@ -447,7 +570,7 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
           const uint32_t pos = n_keep + rank;
           if (pos < M.capT) {
             const float x1 = T1.hx[c.b], y1 = T1.hy[c.b], x2 = T0.hx[c.c], y2 = T0.hy[c.c];
-            const float dz = zl - kLayerZ[l + 1];
+            const float dz = zl - zt[l + 1];
             A.slot[pos] = slot;
             A.key0[pos] = ((uint32_t)(l + 2) << 22) | c.a;
             A.xa[pos] = x2;
@@ -465,15 +588,54 @@ __device__ uint32_t find_event(const EventIO& io, const FindConst& P, FindMem<ID
     }
     if (n_keep + n_new > M.capT) return 1u;
     if (tid == 0) { sc.n_act = n_keep + n_new; sc.n_created += n_new; }
-    __syncthreads();
+    wg_barrier<RING>();
   }
   // close the tracks still active after the first plane
   for (uint32_t t = tid; t < sc.n_act; t += NT) io.nhits[A.slot[t]] = A.n[t];
-  __syncthreads();
+  wg_barrier<RING>();
   return 0u;
 }
 
 // ---------------------------------------------------------------------------
+
+// Azimuth tables of every (event, plane): one 64-lane workgroup per plane,
+// counting sort of the plane's hits by pseudo-angle bucket.  The order inside
+// a bucket is irrelevant: every use scans whole buckets.
+__global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, const float* __restrict__ Y,
+                                                   const uint32_t* __restrict__ hstatus,
+                                                   const uint32_t* __restrict__ lstart,
+                                                   const uint32_t* __restrict__ lnh,
+                                                   const uint64_t* __restrict__ offsets,
+                                                   uint64_t n_pixels, uint32_t* __restrict__ order,
+                                                   uint32_t* __restrict__ bst) {
+  __shared__ uint32_t cnt[kNB], cur[kNB];
+  const uint32_t seg = blockIdx.x, e = seg / kLayers, l = seg % kLayers;
+  const uint64_t b0 = offsets[e], b1 = offsets[e + 1];
+  if (hstatus[e] != 0 || b1 < b0 || b1 > n_pixels) return;
+  const uint32_t n = lnh[seg];
+  const uint64_t base = b0 + lstart[27ull * e + l];
+  uint32_t* bs = bst + (uint64_t)seg * (kNB + 1);
+  for (uint32_t b = threadIdx.x; b < kNB; b += 64) cnt[b] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += 64)
+    atomicAdd(cnt + bucket_of(pangle(X[base + i], Y[base + i]), kNB), 1u);
+  __syncthreads();
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < kNB; b0 += 64) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t c = b < kNB ? cnt[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_scan<64>(c, nullptr, &tot);
+    if (b < kNB) { bs[b] = carry + ex; cur[b] = carry + ex; }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) bs[kNB] = carry;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += 64) {
+    const uint32_t b = bucket_of(pangle(X[base + i], Y[base + i]), kNB);
+    order[base + atomicAdd(cur + b, 1u)] = i;
+  }
+}
 
 struct FindArgs {
   const float* X;  // hit arrays (absolute slots)
@@ -481,6 +643,8 @@ struct FindArgs {
   const uint32_t* hstatus;
   const uint32_t* lstart;
   const uint32_t* lnh;
+  const uint32_t* order;  // azimuth tables (absolute hit slots / per plane)
+  const uint32_t* bst;
   const uint64_t* offsets;
   uint64_t n_pixels;
   uint32_t* n_tracks;
@@ -491,16 +655,31 @@ struct FindArgs {
   uint32_t* esc_list;
 };
 
-// Run one event in the given tier.  Returns true if it must go to the next.
-template <int NT, typename IDX>
-__device__ bool run_event(const FindArgs& a, const FindConst& P, FindMem<IDX>& M, FindScal& sc,
-                          uint32_t e) {
+__device__ __forceinline__ EventIO event_io(const FindArgs& a, uint32_t e) {
   const uint64_t b = a.offsets[e];
-  if (a.hstatus[e] != 0 || a.offsets[e + 1] <= b || a.offsets[e + 1] > a.n_pixels) {
+  return EventIO{a.X + b, a.Y + b, a.lstart + 27ull * e, a.lnh + 26ull * e, a.order + b,
+                 a.bst + (uint64_t)e * kLayers * (kNB + 1), a.nhits, a.hit_idx, b / 3};
+}
+
+__device__ __forceinline__ bool event_skipped(const FindArgs& a, uint32_t e) {
+  const uint64_t b = a.offsets[e], b1 = a.offsets[e + 1];
+  return a.hstatus[e] != 0 || b1 <= b || b1 > a.n_pixels;
+}
+
+// Run one event in the given tier.  Returns true if it must go to the next.
+template <int NT, typename IDX, bool RING>
+__device__ __forceinline__ bool run_event(const FindArgs& a, const FindConst& P,
+                                          const FindMem<IDX, RING>& M, FindScal& sc, uint32_t e) {
+  if (event_skipped(a, e)) {
     if (threadIdx.x == 0) { a.n_tracks[e] = 0; a.tstatus[e] = 0; }
     return false;
   }
-  EventIO io{a.X + b, a.Y + b, a.lstart + 27ull * e, a.lnh + 26ull * e, a.nhits, a.hit_idx, b / 3};
+  EventIO io = event_io(a, e);
+  for (uint32_t i = threadIdx.x; i < 27; i += NT) sc.lstart[i] = io.lstart[i];
+  for (uint32_t i = threadIdx.x; i < 26; i += NT) { sc.lnh[i] = io.lnh[i]; sc.z[i] = kLayerZ[i]; }
+  __syncthreads();
+  io.lstart = sc.lstart;
+  io.lnh = sc.lnh;
   const uint32_t r = find_event<NT>(io, P, M, sc);
   if (r == 1u) return true;
   if (threadIdx.x == 0) {
@@ -510,28 +689,30 @@ __device__ bool run_event(const FindArgs& a, const FindConst& P, FindMem<IDX>& M
   return false;
 }
 
-// LDS tier: one event per workgroup (list == nullptr) or a persistent loop
+// LDS tiers: one event per workgroup (list == nullptr) or a persistent loop
 // over a list of events.
-template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t NB>
+template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t CAPD>
 __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
                                                  const uint32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ list_count) {
-  __shared__ float s_hx[3][CAPL], s_hy[3][CAPL];
-  __shared__ uint16_t s_bl[3][CAPL];
-  __shared__ uint8_t s_used[3][CAPL];
-  __shared__ uint32_t s_best[3][CAPL];
-  __shared__ uint32_t s_bstart[3][NB + 1], s_bcur[3][NB];
+  __shared__ float s_hx[3 * CAPL], s_hy[3 * CAPL];
+  __shared__ uint16_t s_bl[3 * CAPL];
+  __shared__ uint8_t s_used[3 * CAPL];
+  __shared__ uint32_t s_best[3 * CAPL];
+  __shared__ uint32_t s_bstart[3 * (kNB + 1)];
   __shared__ uint32_t t_slot[CAPT], t_key0[CAPT], t_tbest[CAPT], t_tmatch[CAPT];
   __shared__ float t_xa[CAPT], t_ya[CAPT], t_tx[CAPT], t_ty[CAPT];
   __shared__ uint8_t t_la[CAPT], t_n[CAPT], t_skip[CAPT];
   __shared__ Cand s_cand[CAPC];
+  __shared__ uint32_t s_w0[CAPL], s_w1[CAPL], s_wp[CAPL + 1];
+  __shared__ Dbl s_dbl[CAPD];
   __shared__ FindScal sc;
-  FindMem<uint16_t> M;
-  for (int i = 0; i < 3; ++i)
-    M.L[i] = LayerTab<uint16_t>{s_hx[i], s_hy[i], s_bl[i], s_used[i], s_best[i], s_bstart[i], s_bcur[i]};
+  FindMem<uint16_t, true> M;
+  M.w0 = s_w0; M.w1 = s_w1; M.wp = s_wp; M.dbl = s_dbl; M.capD = CAPD;
+  M.hx = s_hx; M.hy = s_hy; M.bl = s_bl; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
   M.T = TrackTab{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
   M.cand = s_cand;
-  M.capL = CAPL; M.capT = CAPT; M.capC = CAPC; M.nb = NB;
+  M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
   const uint32_t count = list ? *list_count : n_events;
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const uint32_t e = list ? list[it] : it;
@@ -540,18 +721,16 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   }
 }
 
-// Workspace tier: tables in global memory, any event size.
+// Workspace tier: any event size.
 constexpr int kGThreads = 256;
-constexpr uint32_t kGBuckets = 1024;
 constexpr uint32_t kGBlocks = 64;
 
 struct GlobalTabs {
-  float* hx; float* hy; uint32_t* bl; uint32_t* best; uint8_t* used;  // [3 * n_pixels]
+  uint32_t* best; uint8_t* used;                                      // [n_pixels]
   uint32_t* slot; uint32_t* key0; uint32_t* tbest; uint32_t* tmatch;  // [n_pixels / 3 + 1]
   float* xa; float* ya; float* tx; float* ty;
   uint8_t* la; uint8_t* n; uint8_t* skip;
-  uint32_t* buckets;  // per block: 3 * (2 * kGBuckets + 1)
-  Cand* cand;         // per block: VELO_MAX_CANDIDATES
+  Cand* cand;  // per block: VELO_MAX_CANDIDATES
 };
 
 __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst P, GlobalTabs g,
@@ -559,18 +738,14 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
                                                            const uint32_t* __restrict__ list_count) {
   __shared__ FindScal sc;
   const uint32_t count = *list_count;
-  uint32_t* bk = g.buckets + (size_t)blockIdx.x * 3 * (2 * kGBuckets + 1);
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const uint32_t e = list[it];
     const uint64_t b = a.offsets[e];
     const uint32_t ne = (uint32_t)(a.offsets[e + 1] - b);
-    FindMem<uint32_t> M;
-    for (int i = 0; i < 3; ++i) {
-      const uint64_t o = 3 * b + (uint64_t)i * ne;
-      uint32_t* bb = bk + i * (2 * kGBuckets + 1);
-      M.L[i] = LayerTab<uint32_t>{g.hx + o, g.hy + o, g.bl + o, g.used + o, g.best + o, bb,
-                                  bb + kGBuckets + 1};
-    }
+    FindMem<uint32_t, false> M;
+    M.hx = nullptr; M.hy = nullptr; M.bl = nullptr; M.bstart = nullptr;
+    M.used = g.used + b;
+    M.best = g.best + b;
     const uint64_t tb = b / 3;
     M.T = TrackTab{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
                    g.la + tb, g.n + tb, g.skip + tb, g.tbest + tb, g.tmatch + tb};
@@ -578,7 +753,9 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.capL = ne;
     M.capT = (uint32_t)((b + ne) / 3 - b / 3);
     M.capC = VELO_MAX_CANDIDATES;
-    M.nb = kGBuckets;
+    M.w0 = M.w1 = M.wp = nullptr;
+    M.dbl = nullptr;
+    M.capD = 0;
     if (run_event<kGThreads>(a, P, M, sc, e) && threadIdx.x == 0) {
       // cannot happen: the tables hold every possible hit and track
       a.n_tracks[e] = 0;
@@ -588,19 +765,52 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
   }
 }
 
+// small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
-constexpr uint32_t kSCapL = 384, kSCapT = 384, kSCapC = 512, kSBuckets = 128;
+constexpr uint32_t kSCapL = 256, kSCapT = 256, kSCapC = 384, kSCapD = 512;
+// large LDS tier: persistent workgroups over the events the small tier hands on
+constexpr int kLThreads = 256;
+constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 2048, kLBlocks = 256;
 
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
-size_t find_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
+struct FindWs {
+  uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *order, *bst;
+  GlobalTabs g;
+};
+
+// carve the workspace; returns the bytes used
+static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, FindWs* out) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* r = w ? w + o : nullptr; o += up256(bytes); return r; };
   const uint64_t nt = n_pixels / 3 + 1;
-  size_t s = up256(4) + up256(4ull * n_events);
-  s += 4 * up256(4ull * 3 * n_pixels) + up256(3 * n_pixels);
-  s += 8 * up256(4ull * nt) + 3 * up256(nt);
-  s += up256(4ull * kGBlocks * 3 * (2 * kGBuckets + 1));
-  s += up256(sizeof(Cand) * (size_t)kGBlocks * VELO_MAX_CANDIDATES);
-  return s;
+  FindWs f;
+  f.esc_count = (uint32_t*)take(4);
+  f.esc_list = (uint32_t*)take(4ull * n_events);
+  f.esc2_count = (uint32_t*)take(4);
+  f.esc2_list = (uint32_t*)take(4ull * n_events);
+  f.order = (uint32_t*)take(4ull * n_pixels);
+  f.bst = (uint32_t*)take(4ull * n_events * kLayers * (kNB + 1));
+  f.g.best = (uint32_t*)take(4ull * n_pixels);
+  f.g.used = (uint8_t*)take(n_pixels);
+  f.g.slot = (uint32_t*)take(4 * nt);
+  f.g.key0 = (uint32_t*)take(4 * nt);
+  f.g.tbest = (uint32_t*)take(4 * nt);
+  f.g.tmatch = (uint32_t*)take(4 * nt);
+  f.g.xa = (float*)take(4 * nt);
+  f.g.ya = (float*)take(4 * nt);
+  f.g.tx = (float*)take(4 * nt);
+  f.g.ty = (float*)take(4 * nt);
+  f.g.la = (uint8_t*)take(nt);
+  f.g.n = (uint8_t*)take(nt);
+  f.g.skip = (uint8_t*)take(nt);
+  f.g.cand = (Cand*)take(sizeof(Cand) * (size_t)kGBlocks * VELO_MAX_CANDIDATES);
+  if (out) *out = f;
+  return o;
+}
+
+size_t find_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
+  return find_ws_layout(nullptr, n_pixels, n_events, nullptr);
 }
 
 FindConst make_find_const(const velo_params* p) {
@@ -620,40 +830,25 @@ FindConst make_find_const(const velo_params* p) {
 hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
                        uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
                        hipStream_t s) {
-  char* w = (char*)ws;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { char* r = w + o; o += up256(bytes); return r; };
-  const uint64_t nt = n_pixels / 3 + 1;
-  uint32_t* esc_count = (uint32_t*)take(4);
-  uint32_t* esc_list = (uint32_t*)take(4ull * n_events);
-  GlobalTabs g;
-  g.hx = (float*)take(4ull * 3 * n_pixels);
-  g.hy = (float*)take(4ull * 3 * n_pixels);
-  g.bl = (uint32_t*)take(4ull * 3 * n_pixels);
-  g.best = (uint32_t*)take(4ull * 3 * n_pixels);
-  g.used = (uint8_t*)take(3 * n_pixels);
-  g.slot = (uint32_t*)take(4 * nt);
-  g.key0 = (uint32_t*)take(4 * nt);
-  g.tbest = (uint32_t*)take(4 * nt);
-  g.tmatch = (uint32_t*)take(4 * nt);
-  g.xa = (float*)take(4 * nt);
-  g.ya = (float*)take(4 * nt);
-  g.tx = (float*)take(4 * nt);
-  g.ty = (float*)take(4 * nt);
-  g.la = (uint8_t*)take(nt);
-  g.n = (uint8_t*)take(nt);
-  g.skip = (uint8_t*)take(nt);
-  g.buckets = (uint32_t*)take(4ull * kGBlocks * 3 * (2 * kGBuckets + 1));
-  g.cand = (Cand*)take(sizeof(Cand) * (size_t)kGBlocks * VELO_MAX_CANDIDATES);
-  FindArgs a{h->x, h->y, h->status, h->layer_start, h->layer_nhits, offsets, n_pixels,
-             t->n_tracks, t->nhits, t->hit_idx, t->status, esc_count, esc_list};
+  FindWs f;
+  find_ws_layout((char*)ws, n_pixels, n_events, &f);
+  FindArgs a{h->x, h->y, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
+             n_pixels, t->n_tracks, t->nhits, t->hit_idx, t->status, f.esc_count, f.esc_list};
   const FindConst c = make_find_const(p);
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, esc_count, 0u, esc_count);
-  hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSBuckets>), dim3(n_events),
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc_count, 0u, f.esc_count);
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
+  hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
+                     h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.bst);
+  hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), dim3(n_events),
                      dim3(kSThreads), 0, s, a, c, n_events, (const uint32_t*)nullptr,
                      (const uint32_t*)nullptr);
-  hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a, c, g, esc_list,
-                     esc_count);
+  FindArgs a2 = a;
+  a2.esc_count = f.esc2_count;
+  a2.esc_list = f.esc2_list;
+  hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(kLBlocks),
+                     dim3(kLThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count);
+  hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a2, c, f.g, f.esc2_list,
+                     f.esc2_count);
   return hipGetLastError();
 }
 

@@ -3,9 +3,8 @@
 // noise from multiple scattering for a constant transverse momentum pt0,
 // then the transport to the point of closest approach to the beamline.
 //
-// One lane per track.  The hits are streamed in decreasing z (the order in
-// which track finding stores them), so the filter keeps only the previous
-// hit; both projections advance in the same loop.  The arithmetic is the
+// One lane per track, hits in decreasing z (the order in which track finding
+// stores them); both projections advance in the same loop.  The arithmetic is the
 // binary32 sequence below in this order (no contraction):
 //   init at hit 1 from hits 0, 1:  u = m1, t = (m1-m0)/d, d = z1-z0,
 //        C00 = s2, C01 = s2/d, C11 = (2 s2)/(d d)
@@ -54,53 +53,71 @@ __device__ __forceinline__ void kf_transport(Kf1& s, float dz) {
   s.c01 = s.c01 + dz * s.c11;
 }
 
-__global__ __launch_bounds__(64) void k_fit(const float* __restrict__ X, const float* __restrict__ Y,
-                                            const uint32_t* __restrict__ key,
-                                            const uint64_t* __restrict__ offsets, uint64_t n_pixels,
-                                            const uint32_t* __restrict__ n_tracks,
-                                            const uint8_t* __restrict__ nhits,
-                                            const uint32_t* __restrict__ hit_idx, FitConst P,
-                                            velo_states o) {
+constexpr int kFitThreads = 128;
+
+// One lane per track; all hit indices, then all hit coordinates of the track
+// are loaded before the filter runs, so a track costs two memory round trips.
+__global__ __launch_bounds__(kFitThreads) void k_fit(const float* __restrict__ X,
+                                                     const float* __restrict__ Y,
+                                                     const uint32_t* __restrict__ key,
+                                                     const uint64_t* __restrict__ offsets,
+                                                     uint64_t n_pixels,
+                                                     const uint32_t* __restrict__ n_tracks,
+                                                     const uint8_t* __restrict__ nhits,
+                                                     const uint32_t* __restrict__ hit_idx,
+                                                     FitConst P, velo_states o) {
   const uint32_t e = blockIdx.x;
   const uint64_t b = offsets[e], end = offsets[e + 1];
   if (end < b || end > n_pixels) return;
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
   const uint32_t nt = n_tracks[e];
-  for (uint32_t t = threadIdx.x; t < nt; t += 64) {
+  for (uint32_t t = threadIdx.x; t < nt; t += kFitThreads) {
     const uint64_t slot = base + t;
     const int n = nhits[slot];
-    const uint32_t* hi = hit_idx + 26ull * slot;
     if (n < 3 || n > kLayers) continue;
-    uint32_t i0 = hi[0], i1 = hi[1];
-    if (i0 >= ne || i1 >= ne) continue;
-    const float x0 = X[b + i0], y0 = Y[b + i0], x1 = X[b + i1], y1 = Y[b + i1];
-    const uint32_t l0 = key[b + i0] >> 22, l1 = key[b + i1] >> 22;
-    const float z0 = kLayerZ[l0 < 26u ? l0 : 25u], z1 = kLayerZ[l1 < 26u ? l1 : 25u];
+    const uint32_t* hi = hit_idx + 26ull * slot;
+    uint32_t idx[kLayers];
+#pragma unroll
+    for (int j = 0; j < kLayers; ++j) idx[j] = j < n ? hi[j] : 0u;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < kLayers; ++j) ok &= idx[j] < ne;
+    if (!ok) continue;
+    float xs[kLayers], ys[kLayers];
+    uint32_t ls[kLayers];
+#pragma unroll
+    for (int j = 0; j < kLayers; ++j) {
+      if (j < n) {
+        xs[j] = X[b + idx[j]];
+        ys[j] = Y[b + idx[j]];
+        const uint32_t lj = key[b + idx[j]] >> 22;
+        ls[j] = lj < 26u ? lj : 25u;
+      }
+    }
+    const float z0 = kLayerZ[ls[0]], z1 = kLayerZ[ls[1]];
     const float d = z1 - z0;
-    const float tx0 = (x1 - x0) / d;
-    const float ty0 = (y1 - y0) / d;
+    const float tx0 = (xs[1] - xs[0]) / d;
+    const float ty0 = (ys[1] - ys[0]) / d;
     const float t2 = tx0 * tx0 + ty0 * ty0;
     const float ms2 = (P.kms * t2) / (1.0f + t2);
     const float s2 = P.sig2;
-    Kf1 sx{x1, tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
-    Kf1 sy{y1, ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+    Kf1 sx{xs[1], tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+    Kf1 sy{ys[1], ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
     float zp = z1;
-    uint32_t lp = l1;
-    bool ok = true;
-    for (int j = 2; j < n; ++j) {
-      const uint32_t ij = hi[j];
-      if (ij >= ne) { ok = false; break; }
-      const uint32_t lj = key[b + ij] >> 22;
-      const float zj = kLayerZ[lj < 26u ? lj : 25u];
-      const float dz = zj - zp;
-      const float dl = (float)((int)lp - (int)lj);
-      kf_step(sx, X[b + ij], dz, dl, ms2, s2);
-      kf_step(sy, Y[b + ij], dz, dl, ms2, s2);
-      zp = zj;
-      lp = lj;
+    uint32_t lp = ls[1];
+#pragma unroll
+    for (int j = 2; j < kLayers; ++j) {
+      if (j < n) {
+        const float zj = kLayerZ[ls[j]];
+        const float dz = zj - zp;
+        const float dl = (float)((int)lp - (int)ls[j]);
+        kf_step(sx, xs[j], dz, dl, ms2, s2);
+        kf_step(sy, ys[j], dz, dl, ms2, s2);
+        zp = zj;
+        lp = ls[j];
+      }
     }
-    if (!ok) continue;
     const float num = sx.u * sx.t + sy.u * sy.t;
     const float den = sx.t * sx.t + sy.t * sy.t;
     const float dzb = den < 1e-12f ? 0.0f : -(num / den);
@@ -140,7 +157,7 @@ FitConst make_fit_const(const velo_params* p) {
 hipError_t launch_fit(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
                       uint32_t n_events, uint64_t n_pixels, const velo_params* p,
                       const velo_states* o, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit, dim3(n_events), dim3(64), 0, s, h->x, h->y, h->key, offsets, n_pixels,
+  hipLaunchKernelGGL(k_fit, dim3(n_events), dim3(kFitThreads), 0, s, h->x, h->y, h->key, offsets, n_pixels,
                      t->n_tracks, t->nhits, t->hit_idx, make_fit_const(p), *o);
   return hipGetLastError();
 }

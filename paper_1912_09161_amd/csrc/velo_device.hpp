@@ -44,9 +44,22 @@ __device__ __forceinline__ uint32_t wave_prefix(bool pred, uint32_t* total) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), lo);
 }
 
+// Workgroup barrier.  LDS_ONLY: orders LDS accesses only, so outstanding
+// global stores (results nobody in the workgroup reads back) do not delay it.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void wg_barrier() {
+  if constexpr (LDS_ONLY) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Workgroup exclusive scan of one value per thread; NT threads, `tmp` holds
 // NT/64 + 1 uint32 of LDS.  Returns the exclusive prefix; *total = sum.
-template <int NT>
+template <int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   constexpr int NW = NT / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -62,7 +75,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32
     return x - v;
   } else {
     if (lane == kWave - 1) tmp[wid] = x;
-    __syncthreads();
+    wg_barrier<LDS_ONLY>();
     uint32_t base = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -70,7 +83,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32
       if (w < wid) base += t;
       tot += t;
     }
-    __syncthreads();
+    wg_barrier<LDS_ONLY>();
     *total = tot;
     return base + x - v;
   }

@@ -139,6 +139,10 @@ class EventBatch:
     def event_pixels(self, e: int) -> np.ndarray:
         return self.pixels[int(self.offsets[e]):int(self.offsets[e + 1])]
 
+    def range(self, e0: int, e1: int) -> "EventBatch":
+        """New batch holding events [e0, e1)."""
+        return _slice(self, int(e0), int(e1))
+
     def select(self, events) -> "EventBatch":
         """New batch holding the given events (in the given order)."""
         ev = np.asarray(events, np.int64)
@@ -351,8 +355,16 @@ def _gen_chunk(cfg: Config, chunk: int, n_ev: int) -> EventBatch:
     )
 
 
-def generate(cfg, n_events: int | None = None, first_event: int = 0) -> EventBatch:
-    """Events [first_event, first_event + n_events) of a config (name or Config)."""
+def _chunk_part(args):
+    cfg, ch, lo, hi = args
+    return _slice(_gen_chunk(cfg, ch, CHUNK), lo, hi)
+
+
+def generate(cfg, n_events: int | None = None, first_event: int = 0, workers: int = 1) -> EventBatch:
+    """Events [first_event, first_event + n_events) of a config (name or Config).
+
+    workers > 1 draws the chunks in a process pool (the result is identical);
+    call it before the process initialises a GPU, since the pool forks."""
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
     if n_events is None:
@@ -361,10 +373,12 @@ def generate(cfg, n_events: int | None = None, first_event: int = 0) -> EventBat
         return _slice(_gen_chunk(cfg, 0, CHUNK), 0, 0)
     c0 = first_event // CHUNK
     c1 = (first_event + n_events - 1) // CHUNK
-    parts = []
-    for ch in range(c0, c1 + 1):
-        b = _gen_chunk(cfg, ch, CHUNK)
-        lo = max(first_event - ch * CHUNK, 0)
-        hi = min(first_event + n_events - ch * CHUNK, CHUNK)
-        parts.append(_slice(b, lo, hi))
+    jobs = [(cfg, ch, max(first_event - ch * CHUNK, 0), min(first_event + n_events - ch * CHUNK, CHUNK))
+            for ch in range(c0, c1 + 1)]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            parts = pool.map(_chunk_part, jobs)
+    else:
+        parts = [_chunk_part(j) for j in jobs]
     return parts[0] if len(parts) == 1 else concat(parts)
