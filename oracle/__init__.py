@@ -13,12 +13,17 @@ from .oracle import (  # noqa: F401
     EV_LAYER_ORDER,
     EV_OVERFLOW,
     MAX_CANDIDATES,
+    N_PARAMS,
     build,
     cluster,
+    features,
     find_tracks,
     fit,
     fit_points,
     layer_z,
     lib_path,
+    mlp_forward,
+    mlp_forward_bf16,
+    mlp_fwd_bwd,
     reconstruct,
 )

@@ -12,7 +12,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "velo_oracle.c")
+_SRCS = [os.path.join(_HERE, "velo_oracle.c"), os.path.join(_HERE, "velo_oracle_mlp.c")]
 _LIB = os.path.join(_HERE, "libvelo_oracle.so")
 
 EV_BAD_WORD = 1
@@ -46,7 +46,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off",
-                               "-fno-fast-math", "-shared", "-fPIC", _SRC, "-o", tmp])
+                               "-fno-fast-math", "-shared", "-fPIC", *_SRCS, "-lm", "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -71,6 +71,15 @@ def _L():
         lib.velo_oracle_fit_points.argtypes = [P, P, P, P, C.c_int32, P, P, P, P, P]
         lib.velo_oracle_layer_z.restype = C.c_float
         lib.velo_oracle_layer_z.argtypes = [C.c_int32]
+        lib.velo_oracle_mlp_nparams.restype = C.c_int32
+        lib.velo_oracle_features.restype = None
+        lib.velo_oracle_features.argtypes = [P, P, C.c_uint32, P, P, P, P, P, P, P, P]
+        lib.velo_oracle_mlp_fwd_bwd.restype = C.c_double
+        lib.velo_oracle_mlp_fwd_bwd.argtypes = [P, P, P, C.c_int64, P]
+        lib.velo_oracle_mlp_forward.restype = None
+        lib.velo_oracle_mlp_forward.argtypes = [P, P, C.c_int64, P]
+        lib.velo_oracle_mlp_forward_bf16.restype = None
+        lib.velo_oracle_mlp_forward_bf16.argtypes = [P, P, P, P, C.c_int64, P]
         _lib = lib
     return _lib
 
@@ -209,3 +218,58 @@ def reconstruct(pixels, offsets, params=None, events=None, threads: int = 1) -> 
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda r: run(*r), ranges))
     return dict(hits=hits, tracks=tracks, states=states)
+
+
+# ---------------------------------------------------------------------------
+# learned track-quality classifier
+
+N_FEATURES = 8
+N_PARAMS = 1377
+
+
+def features(hits, tracks, states, offsets) -> np.ndarray:
+    """Raw features (double) of every track slot, shape (cap, 8)."""
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    cap = len(tracks["nhits"])
+    out = np.zeros((cap, 8), np.float64)
+    key = np.ascontiguousarray(hits["key"], np.uint32)
+    nt = np.ascontiguousarray(tracks["n_tracks"], np.uint32)
+    nh = np.ascontiguousarray(tracks["nhits"], np.uint8)
+    hi = np.ascontiguousarray(tracks["hit_idx"], np.uint32)
+    tx = np.ascontiguousarray(states["tx"], np.float32)
+    ty = np.ascontiguousarray(states["ty"], np.float32)
+    ch = np.ascontiguousarray(states["chi2"], np.float32)
+    nd = np.ascontiguousarray(states["ndof"], np.int32)
+    _L().velo_oracle_features(_p(key), _p(offsets), E, _p(nt), _p(nh), _p(hi), _p(tx), _p(ty),
+                              _p(ch), _p(nd), _p(out))
+    return out
+
+
+def mlp_fwd_bwd(params, g, y):
+    """(mean loss, gradient) in double over standardised samples g (n, 8)."""
+    p = np.ascontiguousarray(params, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    grad = np.zeros(N_PARAMS, np.float64)
+    loss = _L().velo_oracle_mlp_fwd_bwd(_p(p), _p(g), _p(y), len(y), _p(grad))
+    return float(loss), grad
+
+
+def mlp_forward(params, g):
+    p = np.ascontiguousarray(params, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    z = np.zeros(len(g), np.float64)
+    _L().velo_oracle_mlp_forward(_p(p), _p(g), len(g), _p(z))
+    return z
+
+
+def mlp_forward_bf16(params, mean, std, f):
+    """Logits in the GPU inference precision from raw binary32 features f (n, 8)."""
+    p = np.ascontiguousarray(params, np.float32)
+    m = np.ascontiguousarray(mean, np.float32)
+    s = np.ascontiguousarray(std, np.float32)
+    f = np.ascontiguousarray(f, np.float32)
+    z = np.zeros(len(f), np.float32)
+    _L().velo_oracle_mlp_forward_bf16(_p(p), _p(m), _p(s), _p(f), len(f), _p(z))
+    return z

@@ -20,8 +20,8 @@
  *                            (Sec. 2.3.1, third and fourth paragraphs)
  *
  * Every rule the paper leaves open (raw format, connectivity, cuts, tie
- * breaks, filter initialisation) is a written reading of the paper; the
- * list lives with the project's design notes.  Floating point is IEEE
+ * breaks, filter initialisation) is a written reading of the paper, stated
+ * next to the code that implements it.  Floating point is IEEE
  * binary32 in the order written, compiled without contraction, because the
  * same decisions (cuts, sorting) are taken in binary32 by the GPU code.
  *
@@ -108,6 +108,25 @@ int32_t velo_oracle_fit_points(const float* hx, const float* hy, const float* hz
 
 /* float z of layer l */
 float velo_oracle_layer_z(int32_t l);
+
+/* Learned track-quality classifier (velo_oracle_mlp.c): 8 features,
+   8-32-32-1 network, 1377 parameters W1[32][8], b1[32], W2[32][32], b2[32],
+   w3[32], b3.  feat[8*slot]: chi2/ndof, n, missed planes, tx, ty, eta,
+   z first plane, z last plane (double). */
+int32_t velo_oracle_mlp_nparams(void);
+void velo_oracle_features(const uint32_t* key, const uint64_t* offsets, uint32_t n_events,
+                          const uint32_t* n_tracks, const uint8_t* trk_nhits, const uint32_t* hit_idx,
+                          const float* stx, const float* sty, const float* chi2, const int32_t* ndof,
+                          double* feat);
+/* mean BCE-with-logits loss over n standardised samples g[8*n], labels y;
+   grad[1377] receives its gradient (double) */
+double velo_oracle_mlp_fwd_bwd(const double* p, const double* g, const double* y, int64_t n,
+                               double* grad);
+void velo_oracle_mlp_forward(const double* p, const double* g, int64_t n, double* z);
+/* logits in the GPU inference precision (bfloat16 operands, binary32 sums)
+   from raw binary32 features f[8*n] and binary32 parameters */
+void velo_oracle_mlp_forward_bf16(const float* p, const float* mean, const float* stdv,
+                                  const float* f, int64_t n, float* z);
 
 #ifdef __cplusplus
 }
