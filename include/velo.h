@@ -113,7 +113,9 @@ typedef struct {
 
 /* Fitted states at the point of closest approach to the beamline (z axis),
    one per track slot.  cov_x[3*slot] = (var x, cov(x,tx), var tx), cov_y
-   likewise; ndof = 2 n - 4; accepted = plain chi2/ndof cut.                 */
+   likewise; ndof = 2 n - 4.  accepted: the plain chi2/ndof cut (velo_fit) or
+   the learned classifier (velo_fit_mlp).  score (may be NULL for velo_fit):
+   chi2/ndof (velo_fit) or the classifier's logit (velo_fit_mlp, required). */
 typedef struct {
     float* x;
     float* y;
@@ -125,7 +127,25 @@ typedef struct {
     float* chi2;
     int32_t* ndof;
     uint8_t* accepted;
+    float* score;
 } velo_states;
+
+/* Learned track-quality classifier (not in the paper; a learned replacement
+   of the plain cut after the fit).  Features of a track: chi2/ndof, n hits,
+   missed planes = (first plane - last plane + 1) - n, tx, ty,
+   eta = asinh(1/sqrt(tx^2+ty^2)), z of the first and of the last hit plane;
+   standardised g = (f - mean) / std.  Network: h1 = relu(W1 g + b1) (32),
+   h2 = relu(W2 h1 + b2) (32), logit = w3 . h2 + b3.  params: 1377 binary32
+   values W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3.  All three
+   pointers are device pointers; accepted = logit >= threshold.              */
+#define VELO_MLP_FEATURES 8
+#define VELO_MLP_PARAMS 1377
+typedef struct {
+    const float* params;  /* [1377] */
+    const float* mean;    /* [8] */
+    const float* std;     /* [8] */
+    float threshold;
+} velo_mlp;
 
 /* Default working point (see velo_params). */
 void velo_params_default(velo_params* p);
@@ -170,6 +190,78 @@ velo_status velo_reconstruct(const uint32_t* d_pixels, const uint64_t* d_offsets
                              uint64_t n_pixels, const velo_params* params, const velo_hits* hits,
                              const velo_tracks* tracks, const velo_states* states, void* d_ws,
                              size_t ws_bytes, hipStream_t stream);
+
+/* velo_fit followed by the classifier in the same kernel: bfloat16 (round to
+   nearest even) weights and activations into matrix-core instructions with
+   binary32 accumulation; writes score (logit) and accepted.                */
+velo_status velo_fit_mlp(const velo_hits* hits, const velo_tracks* tracks, const uint64_t* d_offsets,
+                         uint32_t n_events, uint64_t n_pixels, const velo_params* params,
+                         const velo_mlp* mlp, const velo_states* out, hipStream_t stream);
+
+/* velo_cluster, velo_find_tracks and velo_fit_mlp enqueued back to back. */
+velo_status velo_reconstruct_mlp(const uint32_t* d_pixels, const uint64_t* d_offsets,
+                                 uint32_t n_events, uint64_t n_pixels, const velo_params* params,
+                                 const velo_mlp* mlp, const velo_hits* hits,
+                                 const velo_tracks* tracks, const velo_states* states, void* d_ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* Raw classifier features (binary32) of every track slot: d_feat[8*slot+k],
+   capacity floor(n_pixels/3) slots; needs states from velo_fit.           */
+velo_status velo_track_features(const velo_hits* hits, const velo_tracks* tracks,
+                                const velo_states* states, const uint64_t* d_offsets,
+                                uint32_t n_events, uint64_t n_pixels, float* d_feat,
+                                hipStream_t stream);
+
+/* Workspace of velo_feature_stats / velo_mlp_fwd_bwd for n samples. */
+size_t velo_mlp_workspace_bytes(uint32_t n_samples);
+
+/* Mean and standard deviation (population) of n feature rows d_feat[8*i+k]. */
+velo_status velo_feature_stats(const float* d_feat, uint64_t n, float* d_mean, float* d_std,
+                               void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* FP32 training: mean binary cross-entropy-with-logits loss over n samples
+   and its gradient.  Sample i is row d_idx[i] (d_idx may be NULL: row i) of
+   d_feat (raw features) with label d_label[row] in {0, 1}.  The sums run in
+   a fixed order, so the result is deterministic.                          */
+velo_status velo_mlp_fwd_bwd(const float* d_params, const float* d_mean, const float* d_std,
+                             const float* d_feat, const float* d_label, const uint32_t* d_idx,
+                             uint32_t n, float* d_grad, float* d_loss, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
+   of the 1377 parameters with moment buffers d_m, d_v.                    */
+velo_status velo_mlp_adam_step(float* d_params, float* d_m, float* d_v, const float* d_grad,
+                               uint32_t step, float lr, hipStream_t stream);
+
+/* Classifier logits of n raw feature rows (the inference of velo_fit_mlp). */
+velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n, float* d_logit,
+                           hipStream_t stream);
+
+/* Batched form.  Events of very uneven occupancy in one launch sequence:
+   the (event, plane) segments and the events are ordered by size, largest
+   first, on the device; clustering and track finding run as persistent
+   workgroups that take items from device counters in that order (work
+   stealing); the whole pipeline is captured once as a HIP graph and replayed
+   while the call's buffers, sizes and parameters stay the same.  On the
+   first call the context autotunes the launch shapes (workgroup sizes and
+   counts of each stage) by timing candidates on that call's batch; that call
+   synchronises the stream.  Results are identical to velo_reconstruct
+   (mlp == NULL) or velo_reconstruct_mlp.  The context owns the tuned
+   configuration and the graph; one context serves one stream at a time.   */
+typedef struct velo_context velo_context;
+velo_status velo_context_create(velo_context** ctx);
+void velo_context_destroy(velo_context* ctx);
+/* out6 = {tuned, clustering grid (0 = one workgroup per segment), large-segment
+   grid, track-finding lanes per event, track-finding grid (0 = one workgroup
+   per event), fit lanes per event}; tuned_ms3 (may be NULL) = best stage times. */
+velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms3);
+size_t velo_batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
+velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels,
+                                     const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
+                                     const velo_params* params, const velo_mlp* mlp,
+                                     const velo_hits* hits, const velo_tracks* tracks,
+                                     const velo_states* states, void* d_ws, size_t ws_bytes,
+                                     hipStream_t stream);
 
 const char* velo_status_string(velo_status s);
 

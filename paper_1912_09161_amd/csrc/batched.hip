@@ -1,0 +1,295 @@
+// batched.hip -- the batched form: events of very uneven occupancy in one
+// launch sequence, with persistent work-stealing workgroups, the whole
+// pipeline captured once as a HIP graph and replayed, and launch shapes picked
+// by an autotuner that times candidates on the live batch.
+//
+// The paper runs its sequence with a custom scheduler and memory manager and
+// one GPU stream per CPU thread (Sec. 2.2, Sec. 3.2); here the device itself
+// balances the work: after validation, k_order_* counting-sort the (event,
+// plane) segments and the events by size, largest first, and the persistent
+// clustering and track-finding workgroups pop items from device counters in
+// that order.  Every item writes its results at positions fixed by the input,
+// so the outputs are identical to the plain form whatever the schedule.
+#include "cluster.hip"
+#include "find.hip"
+#include "fit.hip"
+
+#include <string.h>
+
+namespace velo {
+
+constexpr uint32_t kSegClasses = 64;   // segment size classes (16 words wide)
+constexpr uint32_t kEvClasses = 256;   // event size classes (64 words wide)
+
+struct OrderWs {
+  uint32_t* counters;  // [16]: work-stealing counters (zeroed every run)
+  uint32_t* seg_hist;  // [kSegClasses] then cursors
+  uint32_t* ev_hist;   // [kEvClasses] then cursors
+  uint32_t* seg_order; // [E * 26]
+  uint32_t* ev_order;  // [E]
+};
+
+static size_t up256b(size_t v) { return (v + 255) & ~size_t(255); }
+
+static size_t order_ws_layout(char* w, uint32_t n_events, OrderWs* out) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* r = w ? w + o : nullptr; o += up256b(bytes); return r; };
+  OrderWs f;
+  f.counters = (uint32_t*)take(4 * (16 + kSegClasses + kEvClasses));
+  f.seg_hist = f.counters ? f.counters + 16 : nullptr;
+  f.ev_hist = f.counters ? f.counters + 16 + kSegClasses : nullptr;
+  f.seg_order = (uint32_t*)take(4ull * n_events * kLayers);
+  f.ev_order = (uint32_t*)take(4ull * n_events);
+  if (out) *out = f;
+  return o;
+}
+
+__global__ void k_zero(uint32_t* __restrict__ p, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+__device__ __forceinline__ uint32_t seg_class(const uint64_t* offsets, const uint32_t* status,
+                                              const uint32_t* layer_start, uint64_t n_pixels,
+                                              uint32_t seg) {
+  const uint32_t e = seg / kLayers, l = seg % kLayers;
+  if (status[e] != 0 || !event_ok(offsets, e, n_pixels)) return 0;
+  const uint32_t n = layer_start[27ull * e + l + 1] - layer_start[27ull * e + l];
+  const uint32_t c = n >> 4;
+  return c < kSegClasses ? c : kSegClasses - 1;
+}
+
+__device__ __forceinline__ uint32_t ev_class(const uint64_t* offsets, uint64_t n_pixels, uint32_t e) {
+  if (!event_ok(offsets, e, n_pixels)) return 0;
+  const uint64_t c = (offsets[e + 1] - offsets[e]) >> 6;
+  return c < kEvClasses ? (uint32_t)c : kEvClasses - 1;
+}
+
+__global__ void k_order_hist(const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
+                             const uint32_t* __restrict__ layer_start, uint32_t n_events,
+                             uint64_t n_pixels, OrderWs w) {
+  const uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_events * kLayers) return;
+  atomicAdd(w.seg_hist + seg_class(offsets, status, layer_start, n_pixels, seg), 1u);
+  if (seg % kLayers == 0) atomicAdd(w.ev_hist + ev_class(offsets, n_pixels, seg / kLayers), 1u);
+}
+
+// exclusive scan in descending class order (largest items first)
+__global__ void k_order_scan(OrderWs w) {
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int k = kSegClasses - 1; k >= 0; --k) { const uint32_t v = w.seg_hist[k]; w.seg_hist[k] = c; c += v; }
+  } else if (threadIdx.x == 64) {
+    uint32_t c = 0;
+    for (int k = kEvClasses - 1; k >= 0; --k) { const uint32_t v = w.ev_hist[k]; w.ev_hist[k] = c; c += v; }
+  }
+}
+
+__global__ void k_order_scatter(const uint64_t* __restrict__ offsets,
+                                const uint32_t* __restrict__ status,
+                                const uint32_t* __restrict__ layer_start, uint32_t n_events,
+                                uint64_t n_pixels, OrderWs w) {
+  const uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_events * kLayers) return;
+  w.seg_order[atomicAdd(w.seg_hist + seg_class(offsets, status, layer_start, n_pixels, seg), 1u)] = seg;
+  if (seg % kLayers == 0) {
+    const uint32_t e = seg / kLayers;
+    w.ev_order[atomicAdd(w.ev_hist + ev_class(offsets, n_pixels, e), 1u)] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+struct BatchedCfg {
+  uint32_t small_grid;   // persistent clustering workgroups (0: one per segment)
+  uint32_t mid_grid;
+  int find_threads;
+  uint32_t find_grid;    // persistent track-finding workgroups (0: one per event)
+  int fit_threads;
+};
+
+size_t batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
+  const size_t a = cluster_workspace_bytes(n_pixels, n_events);
+  const size_t b = find_workspace_bytes(n_pixels, n_events);
+  return (a > b ? a : b) + order_ws_layout(nullptr, n_events, nullptr);
+}
+
+struct BatchedCall {
+  const uint32_t* px;
+  const uint64_t* offsets;
+  uint32_t n_events;
+  uint64_t n_pixels;
+  velo_params params;
+  bool has_mlp;
+  velo_mlp mlp;
+  velo_hits hits;
+  velo_tracks tracks;
+  velo_states states;
+  void* ws;
+  size_t ws_bytes;
+};
+
+// ordering + the three stages with the given launch shapes
+static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hipStream_t s,
+                                  int stages = 7) {
+  const size_t main_ws = c.ws_bytes - order_ws_layout(nullptr, c.n_events, nullptr);
+  OrderWs ow;
+  order_ws_layout((char*)c.ws + main_ws, c.n_events, &ow);
+  const uint32_t nseg = c.n_events * kLayers;
+  if (stages & 1) {
+    // clearing, validation, size ordering, clustering
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
+    hipLaunchKernelGGL(k_clear, dim3((c.n_events + 255) / 256), dim3(256), 0, s, c.hits.status,
+                       c.n_events, (uint32_t*)c.ws);
+    if (c.n_pixels > 0)
+      hipLaunchKernelGGL(k_validate, dim3((unsigned)((c.n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
+                         dim3(256), 0, s, c.px, c.offsets, c.n_events, c.n_pixels, c.hits.status,
+                         c.hits.layer_start);
+    hipLaunchKernelGGL(k_order_hist, dim3((nseg + 255) / 256), dim3(256), 0, s, c.offsets, c.hits.status,
+                       c.hits.layer_start, c.n_events, c.n_pixels, ow);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(128), 0, s, ow);
+    hipLaunchKernelGGL(k_order_scatter, dim3((nseg + 255) / 256), dim3(256), 0, s, c.offsets,
+                       c.hits.status, c.hits.layer_start, c.n_events, c.n_pixels, ow);
+    const ClusterCfg cc{k.small_grid, k.mid_grid, ow.seg_order, ow.counters};
+    hipError_t e = launch_cluster_cfg(c.px, c.offsets, c.n_events, c.n_pixels, &c.hits, c.ws, s, cc, true);
+    if (e != hipSuccess) return e;
+  }
+  if (stages & 2) {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 2u);
+    const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2};
+    hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
+                                   c.ws, s, fc);
+    if (e != hipSuccess) return e;
+  }
+  if (stages & 4) {
+    hipError_t e = launch_fit_cfg(&c.hits, &c.tracks, c.offsets, c.n_events, c.n_pixels, &c.params,
+                                  c.has_mlp ? &c.mlp : nullptr, &c.states, s, k.fit_threads);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace velo
+
+// ---------------------------------------------------------------------------
+
+struct velo_context {
+  bool tuned = false;
+  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128};
+  float tuned_ms[3] = {0, 0, 0};
+  // captured graphs of recent call shapes (buffers, sizes, parameters, stream)
+  static constexpr int kGraphs = 32;
+  struct Entry {
+    velo::BatchedCall key;
+    hipStream_t stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  Entry graphs[kGraphs];
+  int n_graphs = 0;
+  uint64_t clock = 0;
+};
+
+namespace {
+
+bool same_call(const velo::BatchedCall& a, const velo::BatchedCall& b) {
+  return memcmp(&a, &b, sizeof(velo::BatchedCall)) == 0;
+}
+
+void drop_entry(velo_context::Entry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+void drop_graphs(velo_context* ctx) {
+  for (int i = 0; i < ctx->n_graphs; ++i) drop_entry(ctx->graphs[i]);
+  ctx->n_graphs = 0;
+}
+
+// time one stage (min of `reps` runs) with events on the stream
+hipError_t time_stage(const velo::BatchedCall& c, const velo::BatchedCfg& k, int stage, hipStream_t s,
+                      int reps, float* ms) {
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&b);
+  if (e != hipSuccess) { (void)hipEventDestroy(a); return e; }
+  float best = 1e30f;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = velo::enqueue_batched(c, k, s, stage);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (t < best) best = t;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = best;
+  return e;
+}
+
+}  // namespace
+
+namespace velo {
+
+// Pick the launch shapes stage by stage on the live batch: clustering first
+// (its output feeds the next stage), then track finding, then the fit.
+static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t s) {
+  BatchedCfg best = ctx->cfg;
+  float t;
+  hipError_t e;
+  // clustering: one workgroup per segment, or persistent grids of several sizes
+  {
+    const uint32_t smalls[] = {0, 1024, 2048, 4096, 8192};
+    const uint32_t mids[] = {256, 512, 1024};
+    float bt = 1e30f;
+    BatchedCfg k = best;
+    for (uint32_t sg : smalls)
+      for (uint32_t mg : mids) {
+        k.small_grid = sg;
+        k.mid_grid = mg;
+        if ((e = time_stage(c, k, 1, s, 3, &t)) != hipSuccess) return e;
+        if (t < bt) { bt = t; best.small_grid = sg; best.mid_grid = mg; }
+      }
+    ctx->tuned_ms[0] = bt;
+    if ((e = enqueue_batched(c, best, s, 1)) != hipSuccess) return e;
+  }
+  // track finding: lanes per event x (one workgroup per event | persistent grid)
+  {
+    const int threads[] = {128, 256};
+    const uint32_t grids[] = {0, 512, 768, 1024, 1536};
+    float bt = 1e30f;
+    BatchedCfg k = best;
+    for (int nt : threads)
+      for (uint32_t g : grids) {
+        k.find_threads = nt;
+        k.find_grid = g;
+        if ((e = time_stage(c, k, 2, s, 3, &t)) != hipSuccess) return e;
+        if (t < bt) { bt = t; best.find_threads = nt; best.find_grid = g; }
+      }
+    ctx->tuned_ms[1] = bt;
+    if ((e = enqueue_batched(c, best, s, 2)) != hipSuccess) return e;
+  }
+  // fit: lanes per event
+  {
+    const int threads[] = {64, 128, 256};
+    float bt = 1e30f;
+    BatchedCfg k = best;
+    for (int nt : threads) {
+      k.fit_threads = nt;
+      if ((e = time_stage(c, k, 4, s, 3, &t)) != hipSuccess) return e;
+      if (t < bt) { bt = t; best.fit_threads = nt; }
+    }
+    ctx->tuned_ms[2] = bt;
+  }
+  ctx->cfg = best;
+  ctx->tuned = true;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace velo
+

@@ -21,7 +21,7 @@
 
 namespace velo {
 
-constexpr uint32_t kSmallCap = 256;   // words per segment handled by one wave
+constexpr uint32_t kSmallCap = 512;   // words per segment handled by one wave
 constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
 constexpr int kMidThreads = 256;
 constexpr uint32_t kDupBit = 0x80000000u;
@@ -259,33 +259,70 @@ __device__ __forceinline__ bool event_ok(const uint64_t* __restrict__ offsets, u
   return a <= b && b <= n_pixels;
 }
 
-__global__ __launch_bounds__(64) void k_small(const uint32_t* __restrict__ px,
-                                              const uint64_t* __restrict__ offsets,
-                                              uint64_t n_pixels, const uint32_t* __restrict__ status,
-                                              const uint32_t* __restrict__ layer_start,
-                                              uint32_t* __restrict__ layer_nhits, HitsOut o,
-                                              uint32_t* __restrict__ mid_count,
-                                              uint32_t* __restrict__ mid_list) {
-  __shared__ uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap], ns[kSmallCap],
-      scs[kSmallCap], srs[kSmallCap];
-  __shared__ uint32_t tmp[2], flag;
-  const uint32_t seg = blockIdx.x;
+struct SmallArgs {
+  const uint32_t* px;
+  const uint64_t* offsets;
+  uint64_t n_pixels;
+  const uint32_t* status;
+  const uint32_t* layer_start;
+  uint32_t* layer_nhits;
+  HitsOut o;
+  uint32_t* mid_count;
+  uint32_t* mid_list;
+};
+
+struct SmallLds {
+  uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap], ns[kSmallCap], scs[kSmallCap],
+      srs[kSmallCap];
+  uint32_t tmp[2], flag;
+};
+
+// One (event, plane) segment with one wave; segments above kSmallCap words
+// are appended to the large-segment list.
+__device__ __forceinline__ void small_segment(const SmallArgs& a, SmallLds& S, uint32_t seg) {
   const uint32_t e = seg / kLayers, l = seg % kLayers;
-  if (status[e] != 0 || !event_ok(offsets, e, n_pixels)) return;
-  const uint64_t b = offsets[e];
-  const uint64_t ne = offsets[e + 1] - b;
+  if (a.status[e] != 0 || !event_ok(a.offsets, e, a.n_pixels)) return;
+  const uint64_t b = a.offsets[e];
+  const uint64_t ne = a.offsets[e + 1] - b;
   if (ne == 0) return;  // empty event: k_finalize writes its outputs
-  const uint32_t s0 = layer_start[27ull * e + l], s1 = layer_start[27ull * e + l + 1];
+  const uint32_t s0 = a.layer_start[27ull * e + l], s1 = a.layer_start[27ull * e + l + 1];
   if (s0 > s1 || s1 > ne) return;  // cannot happen for a validated event
   const uint32_t n = s1 - s0;
   if (n > kSmallCap) {
-    if (threadIdx.x == 0) mid_list[atomicAdd(mid_count, 1u)] = seg;
+    if (threadIdx.x == 0) a.mid_list[atomicAdd(a.mid_count, 1u)] = seg;
     return;
   }
   uint32_t cnt = 0;
   if (n > 0)
-    cnt = cluster_segment<64>(px + b + s0, n, l, srt, par, qs, ns, scs, srs, tmp, &flag, o, b + s0);
-  if (threadIdx.x == 0) layer_nhits[seg] = cnt;
+    cnt = cluster_segment<64>(a.px + b + s0, n, l, S.srt, S.par, S.qs, S.ns, S.scs, S.srs, S.tmp,
+                              &S.flag, a.o, b + s0);
+  if (threadIdx.x == 0) a.layer_nhits[seg] = cnt;
+}
+
+// plain form: one workgroup per segment
+__global__ __launch_bounds__(64) void k_small(SmallArgs a) {
+  __shared__ SmallLds S;
+  small_segment(a, S, blockIdx.x);
+}
+
+// Pop the next work item of a persistent workgroup from a device counter.
+__device__ __forceinline__ uint32_t pop_item(uint32_t* counter, uint32_t* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
+  __syncthreads();
+  const uint32_t it = *slot;
+  __syncthreads();
+  return it;
+}
+
+// batched form: persistent workgroups steal segments in descending-size order
+__global__ __launch_bounds__(64) void k_small_ws(SmallArgs a, const uint32_t* __restrict__ order,
+                                                 uint32_t total, uint32_t* __restrict__ counter) {
+  __shared__ SmallLds S;
+  __shared__ uint32_t item;
+  for (uint32_t it = pop_item(counter, &item); it < total; it = pop_item(counter, &item)) {
+    small_segment(a, S, order[it]);
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict__ px,
@@ -294,12 +331,15 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ layer_nhits, HitsOut o,
                                                      const uint32_t* __restrict__ mid_count,
                                                      const uint32_t* __restrict__ mid_list,
-                                                     uint32_t* __restrict__ ws, uint64_t n_pixels) {
+                                                     uint32_t* __restrict__ ws, uint64_t n_pixels,
+                                                     uint32_t* __restrict__ steal) {
   __shared__ uint32_t srt[kMidCap], par[kMidCap], qs[kMidCap], ns[kMidCap], scs[kMidCap],
       srs[kMidCap];
-  __shared__ uint32_t tmp[kMidThreads / kWave + 1], flag;
+  __shared__ uint32_t tmp[kMidThreads / kWave + 1], flag, item;
   const uint32_t count = *mid_count;
-  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+  // static round robin, or work stealing from a counter when `steal` is given
+  for (uint32_t it = steal ? pop_item(steal, &item) : blockIdx.x; it < count;
+       it = steal ? pop_item(steal, &item) : it + gridDim.x) {
     const uint32_t seg = mid_list[it];
     const uint32_t e = seg / kLayers, l = seg % kLayers;
     const uint64_t b = offsets[e];
@@ -351,32 +391,52 @@ __global__ void k_finalize(const uint64_t* __restrict__ offsets, uint32_t n_even
 
 // ---------------------------------------------------------------------------
 
+// Launch shape of the clustering stage (the batched form's autotuner picks it).
+struct ClusterCfg {
+  uint32_t small_grid;        // 0: one workgroup per segment; else persistent work stealing
+  uint32_t mid_grid;          // workgroups of the large-segment kernel
+  const uint32_t* seg_order;  // descending-size order of the segments (work stealing)
+  uint32_t* counters;         // [2] zeroed work-stealing counters (work stealing)
+};
+
 size_t cluster_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   return up(4) + up(4ull * kLayers * n_events) + up(6ull * 4 * n_pixels);
 }
 
-hipError_t launch_cluster(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
-                          uint64_t n_pixels, const velo_hits* h, void* ws, hipStream_t s) {
+hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
+                              uint64_t n_pixels, const velo_hits* h, void* ws, hipStream_t s,
+                              const ClusterCfg& cfg, bool validated = false) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   char* base = (char*)ws;
   uint32_t* mid_count = (uint32_t*)base;
   uint32_t* mid_list = (uint32_t*)(base + up(4));
   uint32_t* scratch = (uint32_t*)(base + up(4) + up(4ull * kLayers * n_events));
   HitsOut o{h->x, h->y, h->key, h->aux};
-  hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
-                     mid_count);
-  if (n_pixels > 0)
-    hipLaunchKernelGGL(k_validate, dim3((unsigned)((n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
-                       dim3(256), 0, s, px,
-                       offsets, n_events, n_pixels, h->status, h->layer_start);
-  hipLaunchKernelGGL(k_small, dim3(n_events * kLayers), dim3(64), 0, s, px, offsets, n_pixels,
-                     h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list);
-  hipLaunchKernelGGL(k_mid, dim3(512), dim3(kMidThreads), 0, s, px, offsets, h->layer_start,
-                     h->layer_nhits, o, mid_count, mid_list, scratch, n_pixels);
+  if (!validated) {
+    hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
+                       mid_count);
+    if (n_pixels > 0)
+      hipLaunchKernelGGL(k_validate, dim3((unsigned)((n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
+                         dim3(256), 0, s, px, offsets, n_events, n_pixels, h->status, h->layer_start);
+  }
+  SmallArgs a{px, offsets, n_pixels, h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list};
+  if (cfg.small_grid == 0)
+    hipLaunchKernelGGL(k_small, dim3(n_events * kLayers), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_small_ws, dim3(cfg.small_grid), dim3(64), 0, s, a, cfg.seg_order,
+                       n_events * kLayers, cfg.counters);
+  hipLaunchKernelGGL(k_mid, dim3(cfg.mid_grid), dim3(kMidThreads), 0, s, px, offsets, h->layer_start,
+                     h->layer_nhits, o, mid_count, mid_list, scratch, n_pixels,
+                     cfg.small_grid ? cfg.counters + 1 : (uint32_t*)nullptr);
   hipLaunchKernelGGL(k_finalize, dim3((n_events + 255) / 256), dim3(256), 0, s, offsets, n_events,
                      n_pixels, h->status, h->layer_start, h->layer_nhits, h->n_hits);
   return hipGetLastError();
+}
+
+hipError_t launch_cluster(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
+                          uint64_t n_pixels, const velo_hits* h, void* ws, hipStream_t s) {
+  return launch_cluster_cfg(px, offsets, n_events, n_pixels, h, ws, s, ClusterCfg{0, 512, nullptr, nullptr});
 }
 
 }  // namespace velo

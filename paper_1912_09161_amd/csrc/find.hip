@@ -187,6 +187,7 @@ __device__ __forceinline__ uint32_t lda(const uint32_t* p) {
 struct FindScal {
   uint32_t nc;       // candidates found this step (may exceed capC)
   uint32_t nd;       // seed doublets found this step (may exceed capD)
+  uint32_t item;     // work item popped by a persistent workgroup
   uint32_t flag;     // any live candidate left
   uint32_t n_act;    // active tracks
   uint32_t n_created;
@@ -694,7 +695,8 @@ __device__ __forceinline__ bool run_event(const FindArgs& a, const FindConst& P,
 template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t CAPD>
 __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
                                                  const uint32_t* __restrict__ list,
-                                                 const uint32_t* __restrict__ list_count) {
+                                                 const uint32_t* __restrict__ list_count,
+                                                 uint32_t* __restrict__ steal) {
   __shared__ float s_hx[3 * CAPL], s_hy[3 * CAPL];
   __shared__ uint16_t s_bl[3 * CAPL];
   __shared__ uint8_t s_used[3 * CAPL];
@@ -713,8 +715,11 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   M.T = TrackTab{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
   M.cand = s_cand;
   M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
-  const uint32_t count = list ? *list_count : n_events;
-  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+  // work items: events 0..n-1 or list[0..count); round robin over the grid, or
+  // stolen from the `steal` counter (persistent workgroups) when it is given
+  const uint32_t count = list_count ? *list_count : n_events;
+  for (uint32_t it = steal ? pop_item(steal, &sc.item) : blockIdx.x; it < count;
+       it = steal ? pop_item(steal, &sc.item) : it + gridDim.x) {
     const uint32_t e = list ? list[it] : it;
     if (run_event<NT>(a, P, M, sc, e) && threadIdx.x == 0) a.esc_list[atomicAdd(a.esc_count, 1u)] = e;
     __syncthreads();
@@ -827,9 +832,17 @@ FindConst make_find_const(const velo_params* p) {
   return c;
 }
 
-hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
-                       uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
-                       hipStream_t s) {
+// Launch shape of the track-finding stage (the batched form's autotuner picks it).
+struct FindCfg {
+  int small_threads;          // 128 or 256 lanes per event in the small tier
+  uint32_t small_grid;        // 0: one workgroup per event; else persistent work stealing
+  const uint32_t* ev_order;   // descending-size order of the events (work stealing)
+  uint32_t* counters;         // [2] zeroed work-stealing counters (work stealing)
+};
+
+hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
+                           uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
+                           hipStream_t s, const FindCfg& cfg) {
   FindWs f;
   find_ws_layout((char*)ws, n_pixels, n_events, &f);
   FindArgs a{h->x, h->y, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
@@ -839,17 +852,32 @@ hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_e
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
   hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
                      h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.bst);
-  hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), dim3(n_events),
-                     dim3(kSThreads), 0, s, a, c, n_events, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr);
+  const bool ws_mode = cfg.small_grid != 0;
+  const dim3 grid(ws_mode ? cfg.small_grid : n_events);
+  const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
+  uint32_t* steal = ws_mode ? cfg.counters : nullptr;
+  if (cfg.small_threads == 128)
+    hipLaunchKernelGGL((k_find_lds<128, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(128), 0, s, a, c,
+                       n_events, order, (const uint32_t*)nullptr, steal);
+  else
+    hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(kSThreads),
+                       0, s, a, c, n_events, order, (const uint32_t*)nullptr, steal);
   FindArgs a2 = a;
   a2.esc_count = f.esc2_count;
   a2.esc_list = f.esc2_list;
   hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(kLBlocks),
-                     dim3(kLThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count);
+                     dim3(kLThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count,
+                     ws_mode ? cfg.counters + 1 : (uint32_t*)nullptr);
   hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a2, c, f.g, f.esc2_list,
                      f.esc2_count);
   return hipGetLastError();
+}
+
+hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
+                       uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
+                       hipStream_t s) {
+  return launch_find_cfg(h, offsets, n_events, n_pixels, p, t, ws, s,
+                         FindCfg{kSThreads, 0, nullptr, nullptr});
 }
 
 }  // namespace velo

@@ -17,6 +17,7 @@
 //   beamline: dzb = -(x tx + y ty)/(tx tx + ty ty) (0 if the slope is below
 //        1e-6), one plane of slope noise, then transport by dzb.
 #include "velo_device.hpp"
+#include "mlp.hip"
 
 namespace velo {
 
@@ -55,9 +56,104 @@ __device__ __forceinline__ void kf_transport(Kf1& s, float dz) {
 
 constexpr int kFitThreads = 128;
 
-// One lane per track; all hit indices, then all hit coordinates of the track
-// are loaded before the filter runs, so a track costs two memory round trips.
-__global__ __launch_bounds__(kFitThreads) void k_fit(const float* __restrict__ X,
+struct FitOut {
+  float x, y, z, tx, ty, cx[3], cy[3], chi2;
+  int ndof, n, lf, ll;  // hits, first and last plane
+};
+
+// Fit the track in `slot` (hits in decreasing z).  Returns false for a
+// malformed track.  All hit indices, then all coordinates are loaded before
+// the filter runs, so a track costs two memory round trips.
+__device__ __forceinline__ bool fit_track(const float* __restrict__ X, const float* __restrict__ Y,
+                                          const uint32_t* __restrict__ key, uint64_t b, uint32_t ne,
+                                          const uint8_t* __restrict__ nhits,
+                                          const uint32_t* __restrict__ hit_idx, uint64_t slot,
+                                          const FitConst& P, FitOut& o) {
+  const int n = nhits[slot];
+  if (n < 3 || n > kLayers) return false;
+  const uint32_t* hi = hit_idx + 26ull * slot;
+  uint32_t idx[kLayers];
+#pragma unroll
+  for (int j = 0; j < kLayers; ++j) idx[j] = j < n ? hi[j] : 0u;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < kLayers; ++j) ok &= idx[j] < ne;
+  if (!ok) return false;
+  float xs[kLayers], ys[kLayers];
+  uint32_t ls[kLayers];
+#pragma unroll
+  for (int j = 0; j < kLayers; ++j) {
+    if (j < n) {
+      xs[j] = X[b + idx[j]];
+      ys[j] = Y[b + idx[j]];
+      const uint32_t lj = key[b + idx[j]] >> 22;
+      ls[j] = lj < 26u ? lj : 25u;
+    } else {
+      xs[j] = 0.0f;
+      ys[j] = 0.0f;
+      ls[j] = 0u;
+    }
+  }
+  const float z0 = kLayerZ[ls[0]], z1 = kLayerZ[ls[1]];
+  const float d = z1 - z0;
+  const float tx0 = (xs[1] - xs[0]) / d;
+  const float ty0 = (ys[1] - ys[0]) / d;
+  const float t2 = tx0 * tx0 + ty0 * ty0;
+  const float ms2 = (P.kms * t2) / (1.0f + t2);
+  const float s2 = P.sig2;
+  Kf1 sx{xs[1], tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+  Kf1 sy{ys[1], ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
+  float zp = z1;
+  uint32_t lp = ls[1];
+#pragma unroll
+  for (int j = 2; j < kLayers; ++j) {
+    if (j < n) {
+      const float zj = kLayerZ[ls[j]];
+      const float dz = zj - zp;
+      const float dl = (float)((int)lp - (int)ls[j]);
+      kf_step(sx, xs[j], dz, dl, ms2, s2);
+      kf_step(sy, ys[j], dz, dl, ms2, s2);
+      zp = zj;
+      lp = ls[j];
+    }
+  }
+  const float num = sx.u * sx.t + sy.u * sy.t;
+  const float den = sx.t * sx.t + sy.t * sy.t;
+  const float dzb = den < 1e-12f ? 0.0f : -(num / den);
+  sx.c11 = sx.c11 + ms2;
+  sy.c11 = sy.c11 + ms2;
+  kf_transport(sx, dzb);
+  kf_transport(sy, dzb);
+  o.x = sx.u; o.y = sy.u; o.z = zp + dzb; o.tx = sx.t; o.ty = sy.t;
+  o.cx[0] = sx.c00; o.cx[1] = sx.c01; o.cx[2] = sx.c11;
+  o.cy[0] = sy.c00; o.cy[1] = sy.c01; o.cy[2] = sy.c11;
+  o.chi2 = sx.chi2 + sy.chi2;
+  o.ndof = 2 * n - 4;
+  o.n = n;
+  o.lf = (int)ls[0];
+  o.ll = (int)lp;
+  return true;
+}
+
+__device__ __forceinline__ void store_state(const velo_states& o, uint64_t slot, const FitOut& f) {
+  o.x[slot] = f.x;
+  o.y[slot] = f.y;
+  o.z[slot] = f.z;
+  o.tx[slot] = f.tx;
+  o.ty[slot] = f.ty;
+  o.cov_x[3 * slot] = f.cx[0];
+  o.cov_x[3 * slot + 1] = f.cx[1];
+  o.cov_x[3 * slot + 2] = f.cx[2];
+  o.cov_y[3 * slot] = f.cy[0];
+  o.cov_y[3 * slot + 1] = f.cy[1];
+  o.cov_y[3 * slot + 2] = f.cy[2];
+  o.chi2[slot] = f.chi2;
+  o.ndof[slot] = f.ndof;
+}
+
+// Plain form: one lane per track, plain chi2/hit-count cut.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fit(const float* __restrict__ X,
                                                      const float* __restrict__ Y,
                                                      const uint32_t* __restrict__ key,
                                                      const uint64_t* __restrict__ offsets,
@@ -72,76 +168,62 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(const float* __restrict__ X
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
   const uint32_t nt = n_tracks[e];
-  for (uint32_t t = threadIdx.x; t < nt; t += kFitThreads) {
+  for (uint32_t t = threadIdx.x; t < nt; t += NT) {
     const uint64_t slot = base + t;
-    const int n = nhits[slot];
-    if (n < 3 || n > kLayers) continue;
-    const uint32_t* hi = hit_idx + 26ull * slot;
-    uint32_t idx[kLayers];
-#pragma unroll
-    for (int j = 0; j < kLayers; ++j) idx[j] = j < n ? hi[j] : 0u;
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < kLayers; ++j) ok &= idx[j] < ne;
-    if (!ok) continue;
-    float xs[kLayers], ys[kLayers];
-    uint32_t ls[kLayers];
-#pragma unroll
-    for (int j = 0; j < kLayers; ++j) {
-      if (j < n) {
-        xs[j] = X[b + idx[j]];
-        ys[j] = Y[b + idx[j]];
-        const uint32_t lj = key[b + idx[j]] >> 22;
-        ls[j] = lj < 26u ? lj : 25u;
-      }
+    FitOut f;
+    if (!fit_track(X, Y, key, b, ne, nhits, hit_idx, slot, P, f)) continue;
+    store_state(o, slot, f);
+    const float r = f.chi2 / (float)f.ndof;
+    o.accepted[slot] = (uint8_t)(f.n >= 4 ? (r <= P.qc4) : (r <= P.qc3));
+    if (o.score) o.score[slot] = r;
+  }
+}
+
+// Learned form: the fit, the features and the BF16 MFMA classifier in one
+// pass; every wave handles 64 consecutive tracks (all lanes take part in the
+// matrix instructions), accepted = logit >= threshold.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
+                                                         const float* __restrict__ Y,
+                                                         const uint32_t* __restrict__ key,
+                                                         const uint64_t* __restrict__ offsets,
+                                                         uint64_t n_pixels,
+                                                         const uint32_t* __restrict__ n_tracks,
+                                                         const uint8_t* __restrict__ nhits,
+                                                         const uint32_t* __restrict__ hit_idx,
+                                                         FitConst P, const float* __restrict__ mp,
+                                                         const float* __restrict__ mmean,
+                                                         const float* __restrict__ mstd,
+                                                         float threshold, velo_states o) {
+  __shared__ MlpLds L;
+  __shared__ MlpWave W[NT / 64];
+  mlp_load(L, mp, mmean, mstd, NT);
+  __syncthreads();
+  const uint32_t e = blockIdx.x;
+  const uint64_t b = offsets[e], end = offsets[e + 1];
+  if (end < b || end > n_pixels) return;
+  const uint32_t ne = (uint32_t)(end - b);
+  const uint64_t base = b / 3;
+  const uint32_t nt = n_tracks[e];
+  MlpWave& Wv = W[threadIdx.x >> 6];
+  for (uint32_t t0 = 0; t0 < nt; t0 += NT) {
+    const uint32_t t = t0 + threadIdx.x;
+    const uint64_t slot = base + t;
+    FitOut f;
+    const bool ok = t < nt && fit_track(X, Y, key, b, ne, nhits, hit_idx, slot, P, f);
+    float feat[kNF];
+    if (ok) track_features(f.chi2, f.ndof, f.n, f.lf, f.ll, f.tx, f.ty, feat);
+    else
+      for (int k = 0; k < kNF; ++k) feat[k] = L.mean[k];
+    // the whole wave runs the classifier (uniform per wave: t0 is uniform)
+    const bool wave_live = __any(ok);
+    float z = 0.0f;
+    if (wave_live) z = mlp_wave_logit(L, Wv, feat);
+    if (ok) {
+      store_state(o, slot, f);
+      o.accepted[slot] = (uint8_t)(z >= threshold);
+      o.score[slot] = z;
     }
-    const float z0 = kLayerZ[ls[0]], z1 = kLayerZ[ls[1]];
-    const float d = z1 - z0;
-    const float tx0 = (xs[1] - xs[0]) / d;
-    const float ty0 = (ys[1] - ys[0]) / d;
-    const float t2 = tx0 * tx0 + ty0 * ty0;
-    const float ms2 = (P.kms * t2) / (1.0f + t2);
-    const float s2 = P.sig2;
-    Kf1 sx{xs[1], tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
-    Kf1 sy{ys[1], ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
-    float zp = z1;
-    uint32_t lp = ls[1];
-#pragma unroll
-    for (int j = 2; j < kLayers; ++j) {
-      if (j < n) {
-        const float zj = kLayerZ[ls[j]];
-        const float dz = zj - zp;
-        const float dl = (float)((int)lp - (int)ls[j]);
-        kf_step(sx, xs[j], dz, dl, ms2, s2);
-        kf_step(sy, ys[j], dz, dl, ms2, s2);
-        zp = zj;
-        lp = ls[j];
-      }
-    }
-    const float num = sx.u * sx.t + sy.u * sy.t;
-    const float den = sx.t * sx.t + sy.t * sy.t;
-    const float dzb = den < 1e-12f ? 0.0f : -(num / den);
-    sx.c11 = sx.c11 + ms2;
-    sy.c11 = sy.c11 + ms2;
-    kf_transport(sx, dzb);
-    kf_transport(sy, dzb);
-    const float chi2 = sx.chi2 + sy.chi2;
-    const int ndof = 2 * n - 4;
-    o.x[slot] = sx.u;
-    o.y[slot] = sy.u;
-    o.z[slot] = zp + dzb;
-    o.tx[slot] = sx.t;
-    o.ty[slot] = sy.t;
-    o.cov_x[3 * slot] = sx.c00;
-    o.cov_x[3 * slot + 1] = sx.c01;
-    o.cov_x[3 * slot + 2] = sx.c11;
-    o.cov_y[3 * slot] = sy.c00;
-    o.cov_y[3 * slot + 1] = sy.c01;
-    o.cov_y[3 * slot + 2] = sy.c11;
-    o.chi2[slot] = chi2;
-    o.ndof[slot] = ndof;
-    const float r = chi2 / (float)ndof;
-    o.accepted[slot] = (uint8_t)(n >= 4 ? (r <= P.qc4) : (r <= P.qc3));
   }
 }
 
@@ -154,12 +236,40 @@ FitConst make_fit_const(const velo_params* p) {
   return c;
 }
 
+template <int NT>
+static void fit_kernels(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
+                        uint32_t n_events, uint64_t n_pixels, const FitConst& c, const velo_mlp* m,
+                        const velo_states* o, hipStream_t s) {
+  if (m)
+    hipLaunchKernelGGL(k_fit_mlp<NT>, dim3(n_events), dim3(NT), 0, s, h->x, h->y, h->key, offsets,
+                       n_pixels, t->n_tracks, t->nhits, t->hit_idx, c, m->params, m->mean, m->std,
+                       m->threshold, *o);
+  else
+    hipLaunchKernelGGL(k_fit<NT>, dim3(n_events), dim3(NT), 0, s, h->x, h->y, h->key, offsets,
+                       n_pixels, t->n_tracks, t->nhits, t->hit_idx, c, *o);
+}
+
+// threads: 64, 128 or 256 lanes per event (the batched form's autotuner picks it)
+hipError_t launch_fit_cfg(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
+                          uint32_t n_events, uint64_t n_pixels, const velo_params* p,
+                          const velo_mlp* m, const velo_states* o, hipStream_t s, int threads) {
+  const FitConst c = make_fit_const(p);
+  if (threads == 64) fit_kernels<64>(h, t, offsets, n_events, n_pixels, c, m, o, s);
+  else if (threads == 256) fit_kernels<256>(h, t, offsets, n_events, n_pixels, c, m, o, s);
+  else fit_kernels<kFitThreads>(h, t, offsets, n_events, n_pixels, c, m, o, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_fit(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
                       uint32_t n_events, uint64_t n_pixels, const velo_params* p,
                       const velo_states* o, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit, dim3(n_events), dim3(kFitThreads), 0, s, h->x, h->y, h->key, offsets, n_pixels,
-                     t->n_tracks, t->nhits, t->hit_idx, make_fit_const(p), *o);
-  return hipGetLastError();
+  return launch_fit_cfg(h, t, offsets, n_events, n_pixels, p, nullptr, o, s, kFitThreads);
+}
+
+hipError_t launch_fit_mlp(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
+                          uint32_t n_events, uint64_t n_pixels, const velo_params* p,
+                          const velo_mlp* m, const velo_states* o, hipStream_t s) {
+  return launch_fit_cfg(h, t, offsets, n_events, n_pixels, p, m, o, s, kFitThreads);
 }
 
 }  // namespace velo

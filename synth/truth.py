@@ -128,10 +128,10 @@ def track_list(tracks: dict, hits: dict, offsets: np.ndarray):
     slot = slot.astype(np.int64)
     nh = np.asarray(tracks["nhits"])[slot].astype(np.int64)
     hidx = np.asarray(tracks["hit_idx"]).reshape(-1, 26)[slot].astype(np.int64)
-    absidx = offsets[ev][:, None] + hidx
-    keys = np.asarray(hits["key"])[absidx]
     mask = np.arange(26)[None, :] < nh[:, None]
-    keys = np.where(mask, keys, 0)
+    # entries past a track's hit count are unspecified: mask them before indexing
+    absidx = np.where(mask, offsets[ev][:, None] + hidx, 0)
+    keys = np.where(mask, np.asarray(hits["key"])[absidx], 0)
     return ev, slot, nh, keys
 
 
@@ -181,3 +181,32 @@ def metrics(truth: Truth, ev, nh, keys, accepted) -> dict:
         n_reconstructible=truth.n_reconstructible, found=found,
         clone_rate=(n_m - len(pairs)) / max(n_m, 1),
     )
+
+
+def track_labels(truth: Truth, tracks: dict, hits: dict, offsets):
+    """Generator-truth labels of every found track.
+
+    Returns (slot, label, particle_uid, reco_uid): track slots in canonical
+    order, label 1 for tracks matched to a particle by the 70 % rule (clones
+    included) and 0 for ghosts, a unique id (event << 35 | particle) of the
+    matched particle (-1 for ghosts), and the unique ids of the
+    reconstructible particles."""
+    ev, slot, nh, keys = track_list(tracks, hits, offsets)
+    m = match_tracks(truth, ev, nh, keys)
+    uid = np.where(m >= 0, (np.asarray(ev, np.int64) << 35) | np.maximum(m, 0), -1)
+    reco = (truth.reco_ev[truth.reco_ok] << 35) | truth.reco_pid[truth.reco_ok]
+    return slot, (m >= 0).astype(np.float32), uid, reco
+
+
+def efficiency_ghosts(particle_uid, accepted, reco_uid) -> dict:
+    """Efficiency, ghost rate and clone rate of accepted tracks."""
+    acc = np.asarray(accepted, bool)
+    n_acc = int(acc.sum())
+    ghosts = int(np.count_nonzero(acc & (particle_uid < 0)))
+    matched = acc & (particle_uid >= 0)
+    pairs = np.unique(particle_uid[matched])
+    found = int(np.isin(np.unique(reco_uid), pairs).sum())
+    n_m = int(matched.sum())
+    return dict(n_tracks=n_acc, ghosts=ghosts, ghost_rate=ghosts / max(n_acc, 1),
+                efficiency=found / max(len(np.unique(reco_uid)), 1), found=found,
+                clone_rate=(n_m - len(pairs)) / max(n_m, 1))
