@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the batched + classifier form")
     ap.add_argument("--train-events", type=int, default=5500, help="classifier training events (~1M tracks)")
     ap.add_argument("--val-events", type=int, default=2000)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the run, 4 device-to-device copies of this many MiB (calibrates HBM "
+                         "byte counters against a transfer of known size)")
     return ap.parse_args()
 
 
@@ -271,6 +274,15 @@ def main():
         cpu = dict(value=round(sample.n_events / dt, 1), unit="events/s", cores=threads, kind="oracle",
                    sample=f"first {sample.n_events} generated nominal events, cluster+find+fit, "
                           f"{threads} threads over events, {dt:.2f} s wall")
+
+    if args.copy_mb > 0:
+        nb = args.copy_mb << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     forms = dict(plain=dict(value=round(ev_per_s, 1), ms_per_step=round(elapsed * 1e3 / args.steps, 5),
                             physics=physics))

@@ -48,6 +48,9 @@ extern "C" {
 /* Most candidates (seed triplets, or track-hit pairs) one track-finding step
    of one event may produce; beyond it the event gets VELO_EV_OVERFLOW. */
 #define VELO_MAX_CANDIDATES 65536u
+/* Largest n_events of one call (launch grids hold 26 x 64 lanes per event
+ * within 32 bits); larger batches return VELO_ERR_ARG. */
+#define VELO_MAX_EVENTS 2097152u
 
 typedef enum {
     VELO_OK = 0,

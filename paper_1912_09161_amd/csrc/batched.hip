@@ -64,36 +64,76 @@ __device__ __forceinline__ uint32_t ev_class(const uint64_t* offsets, uint64_t n
   return c < kEvClasses ? (uint32_t)c : kEvClasses - 1;
 }
 
-__global__ void k_order_hist(const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
-                             const uint32_t* __restrict__ layer_start, uint32_t n_events,
-                             uint64_t n_pixels, OrderWs w) {
-  const uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= n_events * kLayers) return;
-  atomicAdd(w.seg_hist + seg_class(offsets, status, layer_start, n_pixels, seg), 1u);
-  if (seg % kLayers == 0) atomicAdd(w.ev_hist + ev_class(offsets, n_pixels, seg / kLayers), 1u);
-}
+constexpr int kOrderThreads = 256;
+constexpr uint32_t kOrderItems = 8;  // segments per lane of the ordering kernels
 
-// exclusive scan in descending class order (largest items first)
-__global__ void k_order_scan(OrderWs w) {
-  if (threadIdx.x == 0) {
-    uint32_t c = 0;
-    for (int k = kSegClasses - 1; k >= 0; --k) { const uint32_t v = w.seg_hist[k]; w.seg_hist[k] = c; c += v; }
-  } else if (threadIdx.x == 64) {
-    uint32_t c = 0;
-    for (int k = kEvClasses - 1; k >= 0; --k) { const uint32_t v = w.ev_hist[k]; w.ev_hist[k] = c; c += v; }
+// Per-workgroup LDS histograms of the segment and event size classes of the
+// workgroup's range of segments (kOrderItems * kOrderThreads of them).
+__device__ __forceinline__ void order_block_hist(const uint64_t* offsets, const uint32_t* status,
+                                                 const uint32_t* layer_start, uint32_t n_events,
+                                                 uint64_t n_pixels, uint32_t* sh, uint32_t* eh) {
+  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads) sh[k] = 0;
+  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads) eh[k] = 0;
+  __syncthreads();
+  const uint32_t nseg = n_events * kLayers;
+  const uint32_t s0 = blockIdx.x * kOrderThreads * kOrderItems;
+  for (uint32_t j = 0; j < kOrderItems; ++j) {
+    const uint32_t seg = s0 + j * kOrderThreads + threadIdx.x;
+    if (seg >= nseg) break;
+    atomicAdd(sh + seg_class(offsets, status, layer_start, n_pixels, seg), 1u);
+    if (seg % kLayers == 0) atomicAdd(eh + ev_class(offsets, n_pixels, seg / kLayers), 1u);
   }
+  __syncthreads();
 }
 
-__global__ void k_order_scatter(const uint64_t* __restrict__ offsets,
-                                const uint32_t* __restrict__ status,
-                                const uint32_t* __restrict__ layer_start, uint32_t n_events,
-                                uint64_t n_pixels, OrderWs w) {
-  const uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= n_events * kLayers) return;
-  w.seg_order[atomicAdd(w.seg_hist + seg_class(offsets, status, layer_start, n_pixels, seg), 1u)] = seg;
-  if (seg % kLayers == 0) {
-    const uint32_t e = seg / kLayers;
-    w.ev_order[atomicAdd(w.ev_hist + ev_class(offsets, n_pixels, e), 1u)] = e;
+// class sizes: LDS histograms per workgroup, one global add per non-empty bin
+__global__ __launch_bounds__(kOrderThreads) void k_order_hist(
+    const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
+    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, OrderWs w) {
+  __shared__ uint32_t sh[kSegClasses], eh[kEvClasses];
+  order_block_hist(offsets, status, layer_start, n_events, n_pixels, sh, eh);
+  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads)
+    if (sh[k]) atomicAdd(w.seg_hist + k, sh[k]);
+  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads)
+    if (eh[k]) atomicAdd(w.ev_hist + k, eh[k]);
+}
+
+// exclusive scans in descending class order (largest items first)
+__global__ __launch_bounds__(kOrderThreads) void k_order_scan(OrderWs w) {
+  __shared__ uint32_t tmp[kOrderThreads / kWave + 1];
+  static_assert(kEvClasses == kOrderThreads && kSegClasses <= kOrderThreads, "one class per lane");
+  const uint32_t t = threadIdx.x;
+  uint32_t tot;
+  const uint32_t vs = t < kSegClasses ? w.seg_hist[kSegClasses - 1 - t] : 0u;
+  const uint32_t xs = block_scan<kOrderThreads>(vs, tmp, &tot);
+  if (t < kSegClasses) w.seg_hist[kSegClasses - 1 - t] = xs;
+  const uint32_t ve = w.ev_hist[kEvClasses - 1 - t];
+  const uint32_t xe = block_scan<kOrderThreads>(ve, tmp, &tot);
+  w.ev_hist[kEvClasses - 1 - t] = xe;
+}
+
+// positions: every workgroup reserves one range per non-empty bin, its lanes
+// take positions in it with LDS atomics (order inside a class is arbitrary)
+__global__ __launch_bounds__(kOrderThreads) void k_order_scatter(
+    const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
+    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, OrderWs w) {
+  __shared__ uint32_t sh[kSegClasses], eh[kEvClasses];
+  order_block_hist(offsets, status, layer_start, n_events, n_pixels, sh, eh);
+  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads)
+    if (sh[k]) sh[k] = atomicAdd(w.seg_hist + k, sh[k]);
+  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads)
+    if (eh[k]) eh[k] = atomicAdd(w.ev_hist + k, eh[k]);
+  __syncthreads();
+  const uint32_t nseg = n_events * kLayers;
+  const uint32_t s0 = blockIdx.x * kOrderThreads * kOrderItems;
+  for (uint32_t j = 0; j < kOrderItems; ++j) {
+    const uint32_t seg = s0 + j * kOrderThreads + threadIdx.x;
+    if (seg >= nseg) break;
+    w.seg_order[atomicAdd(sh + seg_class(offsets, status, layer_start, n_pixels, seg), 1u)] = seg;
+    if (seg % kLayers == 0) {
+      const uint32_t e = seg / kLayers;
+      w.ev_order[atomicAdd(eh + ev_class(offsets, n_pixels, e), 1u)] = e;
+    }
   }
 }
 
@@ -140,15 +180,16 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
     hipLaunchKernelGGL(k_clear, dim3((c.n_events + 255) / 256), dim3(256), 0, s, c.hits.status,
                        c.n_events, (uint32_t*)c.ws);
-    if (c.n_pixels > 0)
-      hipLaunchKernelGGL(k_validate, dim3((unsigned)((c.n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
-                         dim3(256), 0, s, c.px, c.offsets, c.n_events, c.n_pixels, c.hits.status,
-                         c.hits.layer_start);
-    hipLaunchKernelGGL(k_order_hist, dim3((nseg + 255) / 256), dim3(256), 0, s, c.offsets, c.hits.status,
-                       c.hits.layer_start, c.n_events, c.n_pixels, ow);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(128), 0, s, ow);
-    hipLaunchKernelGGL(k_order_scatter, dim3((nseg + 255) / 256), dim3(256), 0, s, c.offsets,
-                       c.hits.status, c.hits.layer_start, c.n_events, c.n_pixels, ow);
+    hipLaunchKernelGGL(k_validate, dim3(c.n_events), dim3(kValThreads), 0, s, c.px, c.offsets,
+                       c.n_pixels, c.hits.status, c.hits.layer_start);
+    const uint32_t og = (nseg + kOrderThreads * kOrderItems - 1) / (kOrderThreads * kOrderItems);
+    if (og > 0) {
+      hipLaunchKernelGGL(k_order_hist, dim3(og), dim3(kOrderThreads), 0, s, c.offsets, c.hits.status,
+                         c.hits.layer_start, c.n_events, c.n_pixels, ow);
+      hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderThreads), 0, s, ow);
+      hipLaunchKernelGGL(k_order_scatter, dim3(og), dim3(kOrderThreads), 0, s, c.offsets,
+                         c.hits.status, c.hits.layer_start, c.n_events, c.n_pixels, ow);
+    }
     const ClusterCfg cc{k.small_grid, k.mid_grid, ow.seg_order, ow.counters};
     hipError_t e = launch_cluster_cfg(c.px, c.offsets, c.n_events, c.n_pixels, &c.hits, c.ws, s, cc, true);
     if (e != hipSuccess) return e;

@@ -5,13 +5,13 @@
 //
 // Pipeline (all on one stream, no host round trip):
 //   k_clear     status[e] = 0, work-list counter = 0
-//   k_validate  one thread per word: bad word / hole / plane-order flags and
-//               the plane boundaries (layer_start) of every event
+//   k_validate  one workgroup per event: bad word / hole / plane-order flags
+//               and the plane boundaries (layer_start) of the event
 //   k_small     one 64-lane workgroup per (event, plane) segment of at most
-//               kSmallCap words: LDS sort by address, 8-neighbour union-find
-//               (hook to the smaller index), integer charge sums, ordered
-//               emission by wave ballot/prefix; larger segments are appended
-//               to a work list
+//               kSmallCap words: LDS counting sort by row, 8-neighbour
+//               union-find within two row buckets (roots = smallest
+//               addresses), integer charge sums, emission at the rank of each
+//               cluster key; larger segments are appended to a work list
 //   k_mid       persistent 256-lane workgroups over the work list: the same
 //               algorithm in LDS up to kMidCap words, else in the caller's
 //               workspace at the segment's own word positions
@@ -23,6 +23,7 @@ namespace velo {
 
 constexpr uint32_t kSmallCap = 512;   // words per segment handled by one wave
 constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
+static_assert(kMidCap >= (uint32_t)kPix, "the workspace row table lives at the segment's own positions");
 constexpr int kMidThreads = 256;
 constexpr uint32_t kDupBit = 0x80000000u;
 
@@ -39,40 +40,7 @@ __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Ascending bitonic sort network (flip form: every comparator puts the
-// smaller value at the lower index), over the virtual power-of-two extension
-// of a[0..n); entries >= n act as +infinity and are never touched.
-template <int NT>
-__device__ void sort_u32(uint32_t* a, uint32_t n) {
-  uint32_t P = 1;
-  while (P < n) P <<= 1;
-  const uint32_t half = P >> 1;
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    const uint32_t lh = __builtin_ctz(k >> 1);
-    for (uint32_t t = threadIdx.x; t < half; t += NT) {
-      uint32_t i = ((t >> lh) << (lh + 1)) | (t & ((k >> 1) - 1));
-      uint32_t j = i ^ (k - 1);
-      if (j < n) {
-        uint32_t x = ld(a + i), y = ld(a + j);
-        if (x > y) { a[i] = y; a[j] = x; }
-      }
-    }
-    __syncthreads();
-    for (uint32_t d = k >> 2; d > 0; d >>= 1) {
-      const uint32_t ld2 = __builtin_ctz(d);
-      for (uint32_t t = threadIdx.x; t < half; t += NT) {
-        uint32_t i = ((t >> ld2) << (ld2 + 1)) | (t & (d - 1));
-        uint32_t j = i + d;
-        if (j < n) {
-          uint32_t x = ld(a + i), y = ld(a + j);
-          if (x > y) { a[i] = y; a[j] = x; }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
+// Find the root of x (parent pointers over row-bucket positions).
 __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
   uint32_t p = ld(par + x);
   while (p != x) {
@@ -82,104 +50,148 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
   return x;
 }
 
-// Join the trees of a and b, hooking the larger root under the smaller one,
-// so that every tree's root is its smallest index.
-__device__ __forceinline__ void uf_unite(uint32_t* par, uint32_t a, uint32_t b) {
+// Join the trees of a and b, hooking the root that is larger in (address,
+// position) order under the smaller one, so that every tree's root is its
+// pixel of smallest address.  The order is strict even for repeated
+// addresses, so no cycle can form.
+__device__ __forceinline__ void uf_unite(uint32_t* par, const uint32_t* srt, uint32_t a, uint32_t b) {
   while (true) {
     a = uf_find(par, a);
     b = uf_find(par, b);
     if (a == b) return;
-    if (a > b) { uint32_t t = a; a = b; b = t; }
-    uint32_t old = atomicMin(par + b, a);
-    if (old == b) return;
-    b = old;
+    const uint32_t va = ld(srt + a) >> 4, vb = ld(srt + b) >> 4;
+    if (va > vb || (va == vb && a > b)) { uint32_t t = a; a = b; b = t; }
+    if (atomicCAS(par + b, b, a) == b) return;
   }
 }
 
-// first index j in [lo, hi) with (srt[j] >> 4) >= addr, else hi
-__device__ __forceinline__ uint32_t lower_bound_addr(const uint32_t* srt, uint32_t lo, uint32_t hi,
-                                                     uint32_t addr) {
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if ((ld(srt + mid) >> 4) < addr) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
+// Scratch of one segment of n words (LDS, or the caller's workspace at the
+// segment's own word positions).
+struct SegScratch {
+  uint32_t* rs;   // [kPix] per-row counts, then bucket starts, then bucket ends
+  uint32_t* srt;  // [n] address << 4 | charge, in row-bucket order
+  uint32_t* par;  // [n] union-find parents (row-bucket positions)
+  uint32_t* qs;   // [n] per root: charge sum
+  uint32_t* ns;   // [n] pixel count
+  uint32_t* scs;  // [n] charge-weighted column sum
+  uint32_t* srs;  // [n] charge-weighted row sum
+  uint32_t* pre;  // [n] roots at earlier positions
+  uint32_t* tmp;  // NT/64 + 1 words of LDS (scans)
+  uint32_t* flag; // one word of LDS
+};
 
-// Cluster the n words of one (event, plane) segment with NT lanes.
-// Scratch arrays (n entries each): srt, par, qs, ns, scs, srs; tmp holds
-// NT/64+1 words and flag one word, both in LDS.  Writes hits at
-// out_base + rank (rank = position among the segment's clusters by key).
-// Returns the number of clusters, or kDupBit if two words share an address.
+// Cluster the n words of one (event, plane) segment with NT lanes; writes the
+// hits at out_base + rank (rank = position of the cluster's key among the
+// segment's keys).  Returns the number of clusters, or kDupBit if two words
+// share an address.
+//
+// Pixels are counting-sorted by row (positions inside a row arbitrary), so
+// the 8-neighbours of a pixel are found in two short row buckets; the
+// union-find roots are the smallest addresses; the rank of a root is the
+// number of roots in earlier rows (a prefix over positions, which are row
+// major) plus the roots of its own row with a smaller column.
 template <int NT>
 __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, uint32_t layer,
-                                    uint32_t* srt, uint32_t* par, uint32_t* qs, uint32_t* ns,
-                                    uint32_t* scs, uint32_t* srs, uint32_t* tmp, uint32_t* flag,
-                                    HitsOut o, uint64_t out_base) {
+                                    const SegScratch& S, HitsOut o, uint64_t out_base) {
+  constexpr uint32_t RPL = (kPix + NT - 1) / NT;  // rows per lane in the row scan
   const uint32_t tid = threadIdx.x;
-  // sort value: 22-bit in-plane address (row << 11 | col) then charge
-  for (uint32_t i = tid; i < n; i += NT) {
-    uint32_t v = w[i];
-    srt[i] = ((w_row(v) << 11 | w_col(v)) << 4) | w_charge(v);
-  }
-  if (tid == 0) *flag = 0;
+  uint32_t* rs = S.rs;
+  for (uint32_t r = tid; r < (uint32_t)kPix; r += NT) rs[r] = 0;
+  if (tid == 0) *S.flag = 0;
   __syncthreads();
-  sort_u32<NT>(srt, n);
-  bool dup = false;
-  for (uint32_t i = tid; i < n; i += NT) {
-    uint32_t a = ld(srt + i) >> 4;
-    if (i > 0 && (ld(srt + i - 1) >> 4) == a) dup = true;
-    par[i] = i;
-    qs[i] = 0;
-    ns[i] = 0;
-    scs[i] = 0;
-    srs[i] = 0;
-  }
-  if (dup) atomicOr(flag, 1u);
+  for (uint32_t i = tid; i < n; i += NT) atomicAdd(rs + w_row(w[i]), 1u);
   __syncthreads();
-  if (ld(flag)) return kDupBit;
-
-  // edges to the forward neighbours (r, c+1), (r+1, c-1..c+1)
-  for (uint32_t i = tid; i < n; i += NT) {
-    uint32_t a = ld(srt + i) >> 4;
-    uint32_t r = a >> 11, c = a & 0x7FFu;
-    if (i + 1 < n && (ld(srt + i + 1) >> 4) == a + 1) uf_unite(par, i, i + 1);
-    if (r + 1 < (uint32_t)kPix) {
-      uint32_t lo = ((r + 1) << 11) | (c ? c - 1 : 0u);
-      uint32_t hi = ((r + 1) << 11) | (c + 1 < (uint32_t)kPix ? c + 1 : c);
-      for (uint32_t j = lower_bound_addr(srt, i + 1, n, lo); j < n && (ld(srt + j) >> 4) <= hi; ++j)
-        uf_unite(par, i, j);
+  {  // bucket starts: exclusive prefix over rows, RPL consecutive rows per lane
+    const uint32_t r0 = tid * RPL;
+    uint32_t c[RPL], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < RPL; ++k) {
+      c[k] = r0 + k < (uint32_t)kPix ? ld(rs + r0 + k) : 0u;
+      sum += c[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_scan<NT>(sum, S.tmp, &tot);
+#pragma unroll
+    for (uint32_t k = 0; k < RPL; ++k) {
+      if (r0 + k < (uint32_t)kPix) rs[r0 + k] = run;
+      run += c[k];
     }
   }
   __syncthreads();
-  // flatten and accumulate integer sums at the roots
+  // scatter into row buckets (afterwards rs[r] = end of bucket r)
   for (uint32_t i = tid; i < n; i += NT) {
-    uint32_t r = uf_find(par, i);
-    uint32_t v = ld(srt + i);
-    uint32_t q = v & 15u, a = v >> 4;
-    atomicAdd(qs + r, q);
-    atomicAdd(ns + r, 1u);
-    atomicAdd(scs + r, q * (a & 0x7FFu));
-    atomicAdd(srs + r, q * (a >> 11));
-    if (r != i) par[i] = r;
+    const uint32_t v = w[i];
+    const uint32_t p = atomicAdd(rs + w_row(v), 1u);
+    S.srt[p] = ((w_row(v) << 11 | w_col(v)) << 4) | w_charge(v);
+  }
+  for (uint32_t p = tid; p < n; p += NT) {
+    S.par[p] = p;
+    S.qs[p] = 0;
+    S.ns[p] = 0;
+    S.scs[p] = 0;
+    S.srs[p] = 0;
   }
   __syncthreads();
-  // roots in index (= address) order, compacted by a workgroup prefix count
+  // repeated addresses, and edges to (r, c+1), (r+1, c-1..c+1)
+  bool dup = false;
+  for (uint32_t p = tid; p < n; p += NT) {
+    const uint32_t a = ld(S.srt + p) >> 4;
+    const uint32_t r = a >> 11, c = a & 0x7FFu;
+    const uint32_t b0 = r ? ld(rs + r - 1) : 0u, b1 = ld(rs + r);
+    for (uint32_t q = b0; q < b1; ++q) {
+      const uint32_t aq = ld(S.srt + q) >> 4;
+      if (q != p && aq == a) dup = true;
+      if (aq == a + 1) uf_unite(S.par, S.srt, p, q);
+    }
+    if (r + 1 < (uint32_t)kPix) {
+      const uint32_t e1 = ld(rs + r + 1);
+      for (uint32_t q = b1; q < e1; ++q) {
+        const uint32_t cq = (ld(S.srt + q) >> 4) & 0x7FFu;
+        if (cq + 1 >= c && cq <= c + 1) uf_unite(S.par, S.srt, p, q);
+      }
+    }
+  }
+  if (dup) atomicOr(S.flag, 1u);
+  __syncthreads();
+  if (ld(S.flag)) return kDupBit;
+  // integer sums at the roots
+  for (uint32_t p = tid; p < n; p += NT) {
+    const uint32_t r = uf_find(S.par, p);
+    const uint32_t v = ld(S.srt + p);
+    const uint32_t q = v & 15u, a = v >> 4;
+    atomicAdd(S.qs + r, q);
+    atomicAdd(S.ns + r, 1u);
+    atomicAdd(S.scs + r, q * (a & 0x7FFu));
+    atomicAdd(S.srs + r, q * (a >> 11));
+    if (r != p) S.par[p] = r;
+  }
+  __syncthreads();
+  // roots at earlier positions
   uint32_t carry = 0;
   for (uint32_t b = 0; b < n; b += NT) {
-    uint32_t i = b + tid;
-    bool root = i < n && ld(par + i) == i;
+    const uint32_t p = b + tid;
+    const bool root = p < n && ld(S.par + p) == p;
     uint32_t tot;
-    uint32_t rank = block_scan<NT>(root ? 1u : 0u, tmp, &tot);
-    if (root) {
-      uint64_t slot = out_base + carry + rank;
-      uint32_t Q = ld(qs + i), N = ld(ns + i), SC = ld(scs + i), SR = ld(srs + i);
-      o.x[slot] = ((float)SC / (float)Q - 767.5f) * 0.055f;
-      o.y[slot] = ((float)SR / (float)Q - 767.5f) * 0.055f;
-      o.key[slot] = (layer << 22) | (ld(srt + i) >> 4);
-      o.aux[slot] = ((N < 65535u ? N : 65535u) << 16) | (Q < 65535u ? Q : 65535u);
-    }
+    const uint32_t ex = block_scan<NT>(root ? 1u : 0u, S.tmp, &tot);
+    if (p < n) S.pre[p] = carry + ex;
     carry += tot;
+  }
+  __syncthreads();
+  // rank and emission
+  for (uint32_t p = tid; p < n; p += NT) {
+    if (ld(S.par + p) != p) continue;
+    const uint32_t a = ld(S.srt + p) >> 4;
+    const uint32_t r = a >> 11, c = a & 0x7FFu;
+    const uint32_t b0 = r ? ld(rs + r - 1) : 0u, b1 = ld(rs + r);
+    uint32_t rank = ld(S.pre + b0);
+    for (uint32_t q = b0; q < b1; ++q)
+      if (ld(S.par + q) == q && ((ld(S.srt + q) >> 4) & 0x7FFu) < c) ++rank;
+    const uint64_t slot = out_base + rank;
+    const uint32_t Q = ld(S.qs + p), N = ld(S.ns + p), SC = ld(S.scs + p), SR = ld(S.srs + p);
+    o.x[slot] = ((float)SC / (float)Q - 767.5f) * 0.055f;
+    o.y[slot] = ((float)SR / (float)Q - 767.5f) * 0.055f;
+    o.key[slot] = (layer << 22) | a;
+    o.aux[slot] = ((N < 65535u ? N : 65535u) << 16) | (Q < 65535u ? Q : 65535u);
   }
   return carry;
 }
@@ -192,64 +204,58 @@ __global__ void k_clear(uint32_t* __restrict__ status, uint32_t n_events, uint32
   if (e == 0) *counter = 0;
 }
 
-// largest e in [lo, hi] with offsets[e] <= i (offsets[lo] <= i assumed)
-__device__ __forceinline__ uint32_t event_of(const uint64_t* __restrict__ offsets, uint32_t lo,
-                                             uint32_t hi, uint64_t i) {
-  while (lo < hi) {
-    uint32_t mid = lo + ((hi - lo + 1) >> 1);
-    if (offsets[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
+constexpr int kValThreads = 256;
+constexpr uint32_t kValUnroll = 4;  // words in flight per lane
 
-constexpr uint32_t kValWords = 16;  // words per thread of k_validate
-
-__global__ __launch_bounds__(256) void k_validate(const uint32_t* __restrict__ px,
-                                                  const uint64_t* __restrict__ offsets,
-                                                  uint32_t n_events, uint64_t n_pixels,
-                                                  uint32_t* __restrict__ status,
-                                                  uint32_t* __restrict__ layer_start) {
-  __shared__ uint32_t ev_range[2];
-  const uint64_t span = 256ull * kValWords;
-  const uint64_t i0 = (uint64_t)blockIdx.x * span;
-  if (threadIdx.x < 2) {
-    const uint64_t last = i0 + span - 1 < n_pixels ? i0 + span - 1 : n_pixels - 1;
-    const uint64_t probe = threadIdx.x == 0 ? i0 : last;
-    uint32_t e = 0;
-    if (offsets[0] <= probe) e = event_of(offsets, 0, n_events - 1, probe);
-    ev_range[threadIdx.x] = e;
-  }
-  __syncthreads();
-  uint32_t lo = ev_range[0], hi = ev_range[1];
-  if (hi < lo) hi = lo;  // offsets not monotone: the event is flagged by k_finalize
-#pragma unroll 4
-  for (uint32_t k = 0; k < kValWords; ++k) {
-    const uint64_t i = i0 + threadIdx.x + 256ull * k;
-    if (i >= n_pixels || offsets[0] > i) continue;
-    const uint32_t e = event_of(offsets, lo, hi, i);
-    const uint64_t b = offsets[e], end = offsets[e + 1];
-    if (!(b <= i && i < end) || end > n_pixels) continue;
-    const uint32_t w = px[i];
-    const uint32_t p = (uint32_t)(i - b), n = (uint32_t)(end - b);
-    const uint32_t col = w_col(w), row = w_row(w), lay = w_layer(w), q = w_charge(w);
-    uint32_t flags = 0;
-    const bool valid = !(w >> 31) && lay < (uint32_t)kLayers && row < (uint32_t)kPix &&
-                       col < (uint32_t)kPix && q >= 1u;
-    if (!valid) flags |= VELO_EV_BAD_WORD;
-    else if (in_hole(col, row)) flags |= VELO_EV_HOLE;
-    const uint32_t lc = lay < 26u ? lay : 26u;
-    int lp = -1;
-    if (p > 0) {
-      const uint32_t wp = w_layer(px[i - 1]);
-      if (lay < wp) flags |= VELO_EV_LAYER_ORDER;
-      lp = (int)(wp < 26u ? wp : 26u);
+// One workgroup per event: flags of every word and the plane boundaries of
+// the event (layer_start[27e + l] = index of the first word of plane >= l).
+// Events never share a word, so overlapping or inconsistent offsets of one
+// event cannot disturb another (inconsistent ones are flagged by k_finalize).
+__global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __restrict__ px,
+                                                          const uint64_t* __restrict__ offsets,
+                                                          uint64_t n_pixels,
+                                                          uint32_t* __restrict__ status,
+                                                          uint32_t* __restrict__ layer_start) {
+  const uint32_t e = blockIdx.x;
+  const uint64_t b = offsets[e], end = offsets[e + 1];
+  if (!(b <= end && end <= n_pixels)) return;
+  const uint32_t n = (uint32_t)(end - b);
+  const uint32_t* __restrict__ w = px + b;
+  uint32_t* ls = layer_start + 27ull * e;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t flags = 0;
+  for (uint32_t i0 = 0; i0 < n; i0 += kValThreads * kValUnroll) {
+    uint32_t v[kValUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kValUnroll; ++u) {
+      const uint32_t i = i0 + u * kValThreads + threadIdx.x;
+      v[u] = i < n ? w[i] : 0u;
     }
-    if (flags) atomicOr(status + e, flags);
-    uint32_t* ls = layer_start + 27ull * e;
-    for (int l = lp + 1; l <= (int)lc; ++l) ls[l] = p;
-    if (p == n - 1)
-      for (int l = (int)lc + 1; l <= 26; ++l) ls[l] = n;
+#pragma unroll
+    for (uint32_t u = 0; u < kValUnroll; ++u) {
+      const uint32_t i = i0 + u * kValThreads + threadIdx.x;
+      uint32_t prev = __shfl_up(v[u], 1, kWave);  // word i - 1 (lane 0 loads it)
+      if (lane == 0 && i > 0 && i < n) prev = w[i - 1];
+      if (i >= n) continue;
+      const uint32_t x = v[u];
+      const uint32_t col = w_col(x), row = w_row(x), lay = w_layer(x), q = w_charge(x);
+      const bool valid = !(x >> 31) && lay < (uint32_t)kLayers && row < (uint32_t)kPix &&
+                         col < (uint32_t)kPix && q >= 1u;
+      if (!valid) flags |= VELO_EV_BAD_WORD;
+      else if (in_hole(col, row)) flags |= VELO_EV_HOLE;
+      const uint32_t lc = lay < 26u ? lay : 26u;
+      int lp = -1;
+      if (i > 0) {
+        const uint32_t wp = w_layer(prev);
+        if (lay < wp) flags |= VELO_EV_LAYER_ORDER;
+        lp = (int)(wp < 26u ? wp : 26u);
+      }
+      for (int l = lp + 1; l <= (int)lc; ++l) ls[l] = i;
+      if (i == n - 1)
+        for (int l = (int)lc + 1; l <= 26; ++l) ls[l] = n;
+    }
   }
+  if (flags) atomicOr(status + e, flags);
 }
 
 // offsets of event e are usable (monotone and inside the buffer)
@@ -272,9 +278,13 @@ struct SmallArgs {
 };
 
 struct SmallLds {
+  uint32_t rs[kPix];
   uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap], ns[kSmallCap], scs[kSmallCap],
-      srs[kSmallCap];
+      srs[kSmallCap], pre[kSmallCap];
   uint32_t tmp[2], flag;
+  __device__ SegScratch scratch() {
+    return SegScratch{rs, srt, par, qs, ns, scs, srs, pre, tmp, &flag};
+  }
 };
 
 // One (event, plane) segment with one wave; segments above kSmallCap words
@@ -294,8 +304,7 @@ __device__ __forceinline__ void small_segment(const SmallArgs& a, SmallLds& S, u
   }
   uint32_t cnt = 0;
   if (n > 0)
-    cnt = cluster_segment<64>(a.px + b + s0, n, l, S.srt, S.par, S.qs, S.ns, S.scs, S.srs, S.tmp,
-                              &S.flag, a.o, b + s0);
+    cnt = cluster_segment<64>(a.px + b + s0, n, l, S.scratch(), a.o, b + s0);
   if (threadIdx.x == 0) a.layer_nhits[seg] = cnt;
 }
 
@@ -333,8 +342,8 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ mid_list,
                                                      uint32_t* __restrict__ ws, uint64_t n_pixels,
                                                      uint32_t* __restrict__ steal) {
-  __shared__ uint32_t srt[kMidCap], par[kMidCap], qs[kMidCap], ns[kMidCap], scs[kMidCap],
-      srs[kMidCap];
+  __shared__ uint32_t rs[kPix], srt[kMidCap], par[kMidCap], qs[kMidCap], ns[kMidCap],
+      scs[kMidCap], srs[kMidCap], pre[kMidCap];
   __shared__ uint32_t tmp[kMidThreads / kWave + 1], flag, item;
   const uint32_t count = *mid_count;
   // static round robin, or work stealing from a counter when `steal` is given
@@ -347,15 +356,16 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
     const uint32_t n = s1 - s0;
     uint32_t cnt;
     if (n <= kMidCap) {
-      cnt = cluster_segment<kMidThreads>(px + b + s0, n, l, srt, par, qs, ns, scs, srs, tmp, &flag,
-                                         o, b + s0);
+      const SegScratch S{rs, srt, par, qs, ns, scs, srs, pre, tmp, &flag};
+      cnt = cluster_segment<kMidThreads>(px + b + s0, n, l, S, o, b + s0);
     } else {
-      // scratch in the workspace at the segment's own word positions
+      // scratch in the workspace at the segment's own word positions (n > kPix,
+      // so the row table fits there too)
       const uint64_t p0 = b + s0;
-      cnt = cluster_segment<kMidThreads>(px + p0, n, l, ws + p0, ws + n_pixels + p0,
-                                         ws + 2 * n_pixels + p0, ws + 3 * n_pixels + p0,
-                                         ws + 4 * n_pixels + p0, ws + 5 * n_pixels + p0, tmp, &flag,
-                                         o, p0);
+      const SegScratch S{ws + p0, ws + n_pixels + p0, ws + 2 * n_pixels + p0, ws + 3 * n_pixels + p0,
+                         ws + 4 * n_pixels + p0, ws + 5 * n_pixels + p0, ws + 6 * n_pixels + p0,
+                         ws + 7 * n_pixels + p0, tmp, &flag};
+      cnt = cluster_segment<kMidThreads>(px + p0, n, l, S, o, p0);
     }
     if (threadIdx.x == 0) layer_nhits[seg] = cnt;
     __syncthreads();
@@ -401,7 +411,7 @@ struct ClusterCfg {
 
 size_t cluster_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-  return up(4) + up(4ull * kLayers * n_events) + up(6ull * 4 * n_pixels);
+  return up(4) + up(4ull * kLayers * n_events) + up(8ull * 4 * n_pixels);
 }
 
 hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
@@ -416,9 +426,8 @@ hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint3
   if (!validated) {
     hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
                        mid_count);
-    if (n_pixels > 0)
-      hipLaunchKernelGGL(k_validate, dim3((unsigned)((n_pixels + 256 * kValWords - 1) / (256 * kValWords))),
-                         dim3(256), 0, s, px, offsets, n_events, n_pixels, h->status, h->layer_start);
+    hipLaunchKernelGGL(k_validate, dim3(n_events), dim3(kValThreads), 0, s, px, offsets, n_pixels,
+                       h->status, h->layer_start);
   }
   SmallArgs a{px, offsets, n_pixels, h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list};
   if (cfg.small_grid == 0)

@@ -5,9 +5,11 @@
 //
 // k_phi_tables first sorts the hits of every (event, plane) into kNB azimuth
 // buckets of a monotone pseudo-angle of (x, y) (one wave per plane, counting
-// sort).  Then one workgroup per event walks the planes from z = +750 mm
-// down; the three planes in use (l+2, l+1, l) are staged in a ring of LDS
-// tables: coordinates, bucket order, used flags.  Candidate windows in
+// sort) and writes their coordinates in that order.  Then one workgroup per
+// event walks the planes from z = +750 mm down; the three planes in use
+// (l+2, l+1, l) are staged in a ring of LDS tables indexed by bucket position:
+// coordinates, the hit's index in key order, used flags.  A window scan thus
+// reads the coordinates of consecutive positions directly.  Candidate windows in
 // pseudo-angle are derived conservatively from the exact cuts, so they only
 // accelerate; every decision uses the exact binary32 cut expressions.
 //
@@ -42,13 +44,15 @@ struct FindConst {
 
 constexpr uint32_t kNB = 64;  // azimuth buckets per plane
 
+// One plane, indexed by bucket position p.  The hit's local index (rank of
+// its key in the plane, the order of its event-relative slot) is kr[p].
 template <typename IDX>
 struct LayerTab {
-  const float* hx;        // by local index (= rank of the hit's key in its plane)
+  const float* hx;
   const float* hy;
-  const IDX* bl;          // local indices in bucket order
-  uint8_t* used;          // by local index
-  uint32_t* best;         // by local index: candidate holding the hit in a round
+  const IDX* kr;          // local index of the hit at each position
+  uint8_t* used;
+  uint32_t* best;         // candidate holding the hit in a round
   const uint32_t* bstart; // [kNB + 1] first position of every bucket
 };
 
@@ -63,25 +67,25 @@ struct TrackTab {
   uint8_t* n;       // hits so far
   uint8_t* skip;    // planes missed in a row
   uint32_t* tbest;  // per round: best candidate of the track
-  uint32_t* tmatch; // local index of the hit taken at this plane
+  uint32_t* tmatch; // position of the hit taken at this plane
 };
 
 struct Cand {
   float s;
-  uint32_t a, b, c;  // extension: track, hit; seed: h0, h1, h2 (local indices)
+  uint32_t a, b, c;  // extension: track, hit; seed: h0, h1, h2 (bucket positions)
 };
 
 struct Dbl {
-  uint32_t i01;  // h0 | h1 << 16 (local indices)
+  uint32_t i01;  // h0 | h1 << 16 (bucket positions)
   float tx, ty;
 };
 
 struct EventIO {
-  const float* X;          // hits of the event (absolute base applied)
-  const float* Y;
+  const float* X;          // coordinates of the event's hits in bucket order
+  const float* Y;          // (absolute base applied)
   const uint32_t* lstart;  // [27]
   const uint32_t* lnh;     // [26]
-  const uint32_t* order;   // bucket order of every plane (at the hits' slots)
+  const uint32_t* order;   // local index at every bucket position (at the hits' slots)
   const uint32_t* bst;     // [26 * (kNB + 1)] bucket starts of every plane
   uint8_t* nhits;          // track outputs (absolute slots)
   uint32_t* hit_idx;
@@ -92,12 +96,12 @@ struct EventIO {
 // into a ring of tables stored back to back (stride capL), addressed
 // arithmetically so that the pointers stay in registers.  !RING (workspace
 // tier): coordinates and bucket tables are read in place, used / best live
-// in scratch at the hits' own event-relative slots.
+// in scratch at the plane's own event-relative slots.
 template <typename IDX, bool RING>
 struct FindMem {
   float* hx;
   float* hy;
-  IDX* bl;
+  IDX* kr;
   uint8_t* used;
   uint32_t* best;
   uint32_t* bstart;  // [3 * (kNB + 1)]
@@ -114,7 +118,7 @@ struct FindMem {
   __device__ __forceinline__ LayerTab<IDX> layer(const EventIO& io, int l) const {
     if constexpr (RING) {
       const uint32_t r = (uint32_t)l % 3u, o = r * capL;
-      return LayerTab<IDX>{hx + o, hy + o, bl + o, used + o, best + o, bstart + r * (kNB + 1)};
+      return LayerTab<IDX>{hx + o, hy + o, kr + o, used + o, best + o, bstart + r * (kNB + 1)};
     } else {
       const uint32_t o = io.lstart[l];
       return LayerTab<IDX>{io.X + o, io.Y + o, io.order + o, used + o, best + o,
@@ -185,14 +189,15 @@ __device__ __forceinline__ uint32_t lda(const uint32_t* p) {
 
 // shared scalars of one event
 struct FindScal {
-  uint32_t nc;       // candidates found this step (may exceed capC)
+  uint32_t ncf;      // extension candidates found this step (may exceed capC)
+  uint32_t ncs;      // seed candidates found this step (may exceed capC)
   uint32_t nd;       // seed doublets found this step (may exceed capD)
   uint32_t item;     // work item popped by a persistent workgroup
-  uint32_t flag;     // any live candidate left
+  uint32_t flag[2];  // any live candidate left (alternating by round)
   uint32_t n_act;    // active tracks
   uint32_t n_created;
   uint32_t fail;     // 0 ok, 1 escalate, 2 overflow
-  uint32_t tmp[8];   // scan scratch (NT/64 + 1)
+  uint32_t tmp[2][8];  // scan scratch, two alternating buffers of NT/64 words
   uint32_t lstart[27], lnh[26];  // plane tables of the event
   float z[kLayers];              // plane positions
 };
@@ -200,8 +205,8 @@ struct FindScal {
 // Staging of plane l.  RING tiers: the coordinates, bucket order and bucket
 // starts of the next plane are loaded into registers one step ahead (issue)
 // and stored into the ring table at the start of its step (commit), so the
-// global-memory latency overlaps a whole step.  Used flags are cleared at
-// commit.  Workspace tier: only the used flags are cleared.
+// global-memory latency overlaps a whole step.  Used flags and round winners
+// are cleared at commit.  Workspace tier: only those are cleared.
 template <int NT, typename IDX, bool RING>
 struct PlanePrefetch {
   static constexpr int PF = RING ? 4 : 1;            // hits per lane (capL <= 4 NT)
@@ -230,12 +235,12 @@ struct PlanePrefetch {
     if constexpr (RING) {
       float* hx = const_cast<float*>(t.hx);
       float* hy = const_cast<float*>(t.hy);
-      IDX* bl = const_cast<IDX*>(t.bl);
+      IDX* kr = const_cast<IDX*>(t.kr);
       uint32_t* bsd = const_cast<uint32_t*>(t.bstart);
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; bl[i] = (IDX)o[k]; t.used[i] = 0; }
+        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; t.used[i] = 0; t.best[i] = kNone; }
       }
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
@@ -243,17 +248,59 @@ struct PlanePrefetch {
         if (b <= kNB) bsd[b] = bs[k];
       }
     } else {
-      for (uint32_t i = threadIdx.x; i < n; i += NT) t.used[i] = 0;
+      for (uint32_t i = threadIdx.x; i < n; i += NT) { t.used[i] = 0; t.best[i] = kNone; }
     }
     wg_barrier<RING>();
   }
 };
 
+// Visit positions [p, e) four at a time: the coordinates of a group are
+// loaded together (clamped to e - 1), so their LDS latencies overlap.
+template <typename IDX, typename F>
+__device__ __forceinline__ void scan_range(const LayerTab<IDX>& t, uint32_t p, uint32_t e, F f) {
+  for (; p < e; p += 4) {
+    float x[4], y[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t q = p + j < e ? p + j : e - 1;
+      x[j] = t.hx[q];
+      y[j] = t.hy[q];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (p + j < e) f(p + j, x[j], y[j]);
+  }
+}
+
 template <typename IDX, typename F>
 __device__ __forceinline__ void scan_window(const LayerTab<IDX>& t, Ranges r, F f) {
-  for (uint32_t p = t.bstart[r.b0], e = t.bstart[r.b1 + 1]; p < e; ++p) f((uint32_t)t.bl[p]);
-  if (r.b2 <= r.b3)
-    for (uint32_t p = t.bstart[r.b2], e = t.bstart[r.b3 + 1]; p < e; ++p) f((uint32_t)t.bl[p]);
+  scan_range(t, t.bstart[r.b0], t.bstart[r.b1 + 1], f);
+  if (r.b2 <= r.b3) scan_range(t, t.bstart[r.b2], t.bstart[r.b3 + 1], f);
+}
+
+// Conflict rounds of a greedy rule over nc candidates (Blelloch-Fineman-Shun):
+// every live candidate proposes itself at each of its resources (CAS-min by
+// priority); a candidate that holds all of its resources wins and takes them;
+// repeat while a live candidate is left.  Three barriers per round: the
+// winners' slots are cleared in the same phase that looks for live
+// candidates, and the flag alternates between two words so it is cleared a
+// round ahead.  Invariant: every best/tbest slot is kNone before and after,
+// and both flags are 0.
+template <bool RING, typename PROPOSE, typename ACCEPT, typename CLEAR>
+__device__ __forceinline__ void greedy_rounds(uint32_t nc, FindScal& sc, PROPOSE propose,
+                                              ACCEPT accept, CLEAR clear_and_live) {
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t round = 0; round <= nc; ++round) {
+    propose();
+    wg_barrier<RING>();
+    accept();
+    wg_barrier<RING>();
+    const bool live = clear_and_live();
+    if (live) sc.flag[round & 1] = 1;
+    if (tid == 0) sc.flag[(round + 1) & 1] = 0;
+    wg_barrier<RING>();
+    if (!sc.flag[round & 1]) break;
+  }
 }
 
 // Returns 0 when done, 1 when the event needs a larger tier, 2 on overflow.
@@ -264,7 +311,14 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
   const float* zt = sc.z;
   for (int l = 0; l < kLayers; ++l)
     if (io.lnh[l] > M.capL) return 1u;
-  if (tid == 0) { sc.n_act = 0; sc.n_created = 0; sc.fail = 0; }
+  if (tid == 0) {
+    sc.n_act = 0; sc.n_created = 0; sc.fail = 0; sc.ncf = 0; sc.flag[0] = 0; sc.flag[1] = 0;
+  }
+  uint32_t sbuf = 0;  // alternating scan buffer
+  auto scan = [&](uint32_t v, uint32_t* tot) {
+    sbuf ^= 1u;
+    return block_scan1<NT, RING>(v, sc.tmp[sbuf], tot);
+  };
   PlanePrefetch<NT, IDX, RING> pf;
   pf.issue(io, kLayers - 1, M.capL);
   wg_barrier<RING>();
@@ -278,73 +332,74 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     const uint32_t n_act = sc.n_act;
 
     // ---- 1. extend active tracks into plane l ----
-    if (tid == 0) sc.nc = 0;
-    for (uint32_t t = tid; t < n_act; t += NT) { A.tmatch[t] = kNone; }
-    wg_barrier<RING>();
+    // (the seed counters were last read a step ago, several barriers back)
+    if (tid == 0) { sc.ncs = 0; sc.nd = 0; }
     for (uint32_t t = tid; t < n_act; t += NT) {
+      A.tmatch[t] = kNone;
+      A.tbest[t] = kNone;
       const float xa = A.xa[t], ya = A.ya[t], txf = A.tx[t], tyf = A.ty[t];
       const float za = zt[A.la[t]];
       const float d = zl - za;
       const float xp = xa + txf * d;
       const float yp = ya + tyf * d;
       Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
-      scan_window(T0, r, [&](uint32_t h) {
-        float dx = T0.hx[h] - xp, dy = T0.hy[h] - yp;
+      scan_window(T0, r, [&](uint32_t h, float xh, float yh) {
+        float dx = xh - xp, dy = yh - yp;
         float s = dx * dx + dy * dy;
         if (s <= P.s_fwd) {
-          uint32_t k = atomicAdd(&sc.nc, 1u);
+          uint32_t k = atomicAdd(&sc.ncf, 1u);
           if (k < M.capC) M.cand[k] = Cand{s, t, h, 0u};
         }
       });
     }
     wg_barrier<RING>();
     {
-      const uint32_t nc = sc.nc;
+      const uint32_t nc = sc.ncf;
       if (nc > VELO_MAX_CANDIDATES) return 2u;
       if (nc > M.capC) return 1u;
-      // greedy matching by (s, first-hit key of the track, hit key)
-      auto less_hit = [&](uint32_t i, uint32_t j) {
-        const Cand ci = M.cand[i], cj = M.cand[j];
-        if (ci.s != cj.s) return ci.s < cj.s;
-        return A.key0[ci.a] < A.key0[cj.a];
-      };
-      auto less_trk = [&](uint32_t i, uint32_t j) {
-        const Cand ci = M.cand[i], cj = M.cand[j];
-        if (ci.s != cj.s) return ci.s < cj.s;
-        return ci.b < cj.b;
-      };
-      // every round accepts the smallest live candidate, so nc rounds suffice
-      for (uint32_t round = 0; round < nc; ++round) {
-        for (uint32_t h = tid; h < n0; h += NT) T0.best[h] = kNone;
-        for (uint32_t t = tid; t < n_act; t += NT) A.tbest[t] = kNone;
-        if (tid == 0) sc.flag = 0;
-        wg_barrier<RING>();
-        for (uint32_t k = tid; k < nc; k += NT) {
-          const Cand c = M.cand[k];
-          if (A.tmatch[c.a] == kNone && !T0.used[c.b]) {
-            cas_min(T0.best + c.b, k, less_hit);
-            cas_min(A.tbest + c.a, k, less_trk);
-          }
-        }
-        wg_barrier<RING>();
-        for (uint32_t k = tid; k < nc; k += NT) {
-          const Cand c = M.cand[k];
-          if (A.tmatch[c.a] == kNone && !T0.used[c.b] && lda(T0.best + c.b) == k &&
-              lda(A.tbest + c.a) == k) {
-            A.tmatch[c.a] = c.b;
-            T0.used[c.b] = 1;
-          }
-        }
-        wg_barrier<RING>();
-        bool live = false;
-        for (uint32_t k = tid; k < nc; k += NT) {
-          const Cand c = M.cand[k];
-          if (A.tmatch[c.a] == kNone && !T0.used[c.b]) live = true;
-        }
-        if (live) sc.flag = 1;
-        wg_barrier<RING>();
-        if (!sc.flag) break;
-        wg_barrier<RING>();
+      if (nc > 0) {
+        // greedy matching by (s, first-hit key of the track, hit key)
+        auto less_hit = [&](uint32_t i, uint32_t j) {
+          const Cand ci = M.cand[i], cj = M.cand[j];
+          if (ci.s != cj.s) return ci.s < cj.s;
+          return A.key0[ci.a] < A.key0[cj.a];
+        };
+        auto less_trk = [&](uint32_t i, uint32_t j) {
+          const Cand ci = M.cand[i], cj = M.cand[j];
+          if (ci.s != cj.s) return ci.s < cj.s;
+          return T0.kr[ci.b] < T0.kr[cj.b];
+        };
+        auto live = [&](const Cand& c) { return A.tmatch[c.a] == kNone && !T0.used[c.b]; };
+        greedy_rounds<RING>(
+            nc, sc,
+            [&] {
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                if (live(c)) {
+                  cas_min(T0.best + c.b, k, less_hit);
+                  cas_min(A.tbest + c.a, k, less_trk);
+                }
+              }
+            },
+            [&] {
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                if (live(c) && lda(T0.best + c.b) == k && lda(A.tbest + c.a) == k) {
+                  A.tmatch[c.a] = c.b;
+                  T0.used[c.b] = 1;
+                }
+              }
+            },
+            [&] {
+              bool any = false;
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                T0.best[c.b] = kNone;
+                A.tbest[c.a] = kNone;
+                if (live(c)) any = true;
+              }
+              return any;
+            });
       }
     }
     // apply: append matched hits, count misses
@@ -352,7 +407,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       const uint32_t h = A.tmatch[t];
       if (h != kNone) {
         const uint32_t nn = A.n[t];
-        io.hit_idx[26ull * A.slot[t] + nn] = base0 + h;
+        io.hit_idx[26ull * A.slot[t] + nn] = base0 + (uint32_t)T0.kr[h];
         const float xh = T0.hx[h], yh = T0.hy[h];
         const float dz = zl - zt[A.la[t]];
         A.tx[t] = (xh - A.xa[t]) / dz;
@@ -379,8 +434,6 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       n1 = io.lnh[l + 1];
       n2 = io.lnh[l + 2];
       const float z0 = zt[l + 2], z1 = zt[l + 1], z2 = zl;
-      if (tid == 0) { sc.nc = 0; sc.nd = 0; }
-      wg_barrier<RING>();
       const float dz01 = z1 - z0;
       const float d12 = z2 - z1;
       // third hit of a doublet (h0, h1): unused, within sqrt(s_seed) of the line
@@ -388,19 +441,17 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         const float xp = T1.hx[i1] + tx * d12;
         const float yp = T1.hy[i1] + ty * d12;
         Ranges r2 = window(pangle(xp, yp), point_window(xp, yp, P.rho_seed), kNB);
-        scan_window(T0, r2, [&](uint32_t i2) {
-          if (T0.used[i2]) return;
-          const float dx = T0.hx[i2] - xp, dy = T0.hy[i2] - yp;
+        scan_window(T0, r2, [&](uint32_t i2, float x2, float y2) {
+          const float dx = x2 - xp, dy = y2 - yp;
           const float s = dx * dx + dy * dy;
-          if (s <= P.s_seed) {
-            uint32_t k = atomicAdd(&sc.nc, 1u);
+          if (s <= P.s_seed && !T0.used[i2]) {
+            uint32_t k = atomicAdd(&sc.ncs, 1u);
             if (k < M.capC) M.cand[k] = Cand{s, i0, i1, i2};
           }
         });
       };
       // doublet cuts of (h0 on l+2, h1 on l+1); returns false if rejected
-      auto doublet = [&](uint32_t i0, uint32_t i1, float& tx, float& ty) {
-        const float x0 = T2.hx[i0], y0 = T2.hy[i0], x1 = T1.hx[i1], y1 = T1.hy[i1];
+      auto doublet = [&](float x0, float y0, float x1, float y1, float& tx, float& ty) {
         tx = (x1 - x0) / dz01;
         ty = (y1 - y0) / dz01;
         if (!(fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t)) return false;
@@ -426,13 +477,14 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
             cnt = l0 + l1;
           }
           uint32_t tot;
-          const uint32_t ex = block_scan<NT, RING>(cnt, sc.tmp, &tot);
+          const uint32_t ex = scan(cnt, &tot);
           if (i1 < n1) M.wp[i1] = carry + ex;
           carry += tot;
         }
         if (tid == 0) M.wp[n1] = carry;
         wg_barrier<RING>();
-        // (b) all (h1, h0) pairs, split evenly over the lanes in contiguous chunks
+        // (b) all (h1, h0) pairs, split evenly over the lanes in contiguous chunks;
+        // four pairs of one middle hit per step, their loads issued together
         const uint32_t total = carry, per = (total + NT - 1) / NT;
         uint32_t j = tid * per;
         const uint32_t jend = j + per < total ? j + per : total;
@@ -442,17 +494,35 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
             const uint32_t mid = (lo + hi + 1) >> 1;
             if (M.wp[mid] <= j) lo = mid; else hi = mid - 1;
           }
-          uint32_t i1 = lo;
-          for (; j < jend; ++j) {
-            while (M.wp[i1 + 1] <= j) ++i1;
-            const uint32_t k = j - M.wp[i1], w0 = M.w0[i1], l0 = w0 >> 16;
-            const uint32_t p = k < l0 ? (w0 & 0xFFFFu) + k : (M.w1[i1] & 0xFFFFu) + (k - l0);
-            const uint32_t i0 = T2.bl[p];
-            if (T2.used[i0]) continue;
-            float tx, ty;
-            if (!doublet(i0, i1, tx, ty)) continue;
-            const uint32_t d = atomicAdd(&sc.nd, 1u);
-            if (d < M.capD) M.dbl[d] = Dbl{i0 | (i1 << 16), tx, ty};
+          for (uint32_t i1 = lo; j < jend; ++i1) {
+            const uint32_t wb = M.wp[i1], we = M.wp[i1 + 1];
+            if (we <= j) continue;
+            const uint32_t w0 = M.w0[i1], w1 = M.w1[i1], l0 = w0 >> 16;
+            const float x1 = T1.hx[i1], y1 = T1.hy[i1];
+            const uint32_t stop = we < jend ? we : jend;
+            for (uint32_t g = j; g < stop; g += 4) {
+              uint32_t pj[4];
+              float x0[4], y0[4];
+              uint8_t u0[4];
+#pragma unroll
+              for (uint32_t q = 0; q < 4; ++q) {
+                const uint32_t jj = g + q < stop ? g + q : stop - 1;
+                const uint32_t k = jj - wb;
+                pj[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
+                x0[q] = T2.hx[pj[q]];
+                y0[q] = T2.hy[pj[q]];
+                u0[q] = T2.used[pj[q]];
+              }
+#pragma unroll
+              for (uint32_t q = 0; q < 4; ++q) {
+                if (g + q >= stop || u0[q]) continue;
+                float tx, ty;
+                if (!doublet(x0[q], y0[q], x1, y1, tx, ty)) continue;
+                const uint32_t d = atomicAdd(&sc.nd, 1u);
+                if (d < M.capD) M.dbl[d] = Dbl{pj[q] | (i1 << 16), tx, ty};
+              }
+            }
+            j = stop;
           }
         }
         wg_barrier<RING>();
@@ -467,69 +537,74 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         for (uint32_t i1 = tid; i1 < n1; i1 += NT) {
           if (T1.used[i1]) continue;
           const Ranges r0 = window(pangle(T1.hx[i1], T1.hy[i1]), P.win_doublet, kNB);
-          scan_window(T2, r0, [&](uint32_t i0) {
+          const float x1 = T1.hx[i1], y1 = T1.hy[i1];
+          scan_window(T2, r0, [&](uint32_t i0, float x0, float y0) {
             if (T2.used[i0]) return;
             float tx, ty;
-            if (doublet(i0, i1, tx, ty)) triplets(i0, i1, tx, ty);
+            if (doublet(x0, y0, x1, y1, tx, ty)) triplets(i0, i1, tx, ty);
           });
         }
       }
       wg_barrier<RING>();
-      const uint32_t nc = sc.nc;
+      const uint32_t nc = sc.ncs;
       if (nc > VELO_MAX_CANDIDATES) return 2u;
       if (nc > M.capC) return 1u;
-      // greedy independent set by (s, key1, key0, key2)
-      auto less_seed = [&](uint32_t i, uint32_t j) {
-        const Cand ci = M.cand[i], cj = M.cand[j];
-        if (ci.s != cj.s) return ci.s < cj.s;
-        if (ci.b != cj.b) return ci.b < cj.b;
-        if (ci.a != cj.a) return ci.a < cj.a;
-        return ci.c < cj.c;
-      };
-      auto alive = [&](const Cand& c) { return !T2.used[c.a] && !T1.used[c.b] && !T0.used[c.c]; };
-      for (uint32_t round = 0; round < nc; ++round) {
-        for (uint32_t h = tid; h < n2; h += NT) T2.best[h] = kNone;
-        for (uint32_t h = tid; h < n1; h += NT) T1.best[h] = kNone;
-        for (uint32_t h = tid; h < n0; h += NT) T0.best[h] = kNone;
-        if (tid == 0) sc.flag = 0;
-        wg_barrier<RING>();
-        for (uint32_t k = tid; k < nc; k += NT) {
-          const Cand c = M.cand[k];
-          if (alive(c)) {
-            cas_min(T2.best + c.a, k, less_seed);
-            cas_min(T1.best + c.b, k, less_seed);
-            cas_min(T0.best + c.c, k, less_seed);
-          }
-        }
-        wg_barrier<RING>();
-        for (uint32_t k = tid; k < nc; k += NT) {
-          const Cand c = M.cand[k];
-          if (alive(c) && lda(T2.best + c.a) == k && lda(T1.best + c.b) == k &&
-              lda(T0.best + c.c) == k) {
-            T2.used[c.a] = 1;
-            T1.used[c.b] = 1;
-            T0.used[c.c] = 1;
-            M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
-          }
-        }
-        wg_barrier<RING>();
-        bool live = false;
+      if (nc > 0) {
+        // greedy independent set by (s, key1, key0, key2)
+        auto less_seed = [&](uint32_t i, uint32_t j) {
+          const Cand ci = M.cand[i], cj = M.cand[j];
+          if (ci.s != cj.s) return ci.s < cj.s;
+          if (ci.b != cj.b) return T1.kr[ci.b] < T1.kr[cj.b];
+          if (ci.a != cj.a) return T2.kr[ci.a] < T2.kr[cj.a];
+          return T0.kr[ci.c] < T0.kr[cj.c];
+        };
+        auto alive = [&](const Cand& c) { return !T2.used[c.a] && !T1.used[c.b] && !T0.used[c.c]; };
+        greedy_rounds<RING>(
+            nc, sc,
+            [&] {
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                if (alive(c)) {
+                  cas_min(T2.best + c.a, k, less_seed);
+                  cas_min(T1.best + c.b, k, less_seed);
+                  cas_min(T0.best + c.c, k, less_seed);
+                }
+              }
+            },
+            [&] {
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                if (alive(c) && lda(T2.best + c.a) == k && lda(T1.best + c.b) == k &&
+                    lda(T0.best + c.c) == k) {
+                  T2.used[c.a] = 1;
+                  T1.used[c.b] = 1;
+                  T0.used[c.c] = 1;
+                  M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
+                }
+              }
+            },
+            [&] {
+              bool any = false;
+              for (uint32_t k = tid; k < nc; k += NT) {
+                const Cand c = M.cand[k];
+                T2.best[c.a] = kNone;
+                T1.best[c.b] = kNone;
+                T0.best[c.c] = kNone;
+                if (alive(c)) any = true;
+              }
+              return any;
+            });
+        // accepted seed of each h0, stored by the local index of h0 (the slots
+        // are clear; nothing reads plane l+2 by position any more)
         for (uint32_t k = tid; k < nc; k += NT)
-          if (alive(M.cand[k])) live = true;
-        if (live) sc.flag = 1;
-        wg_barrier<RING>();
-        if (!sc.flag) break;
+          if (M.cand[k].s < 0.0f) T2.best[T2.kr[M.cand[k].a]] = k;
         wg_barrier<RING>();
       }
-      // accepted seed of each h0 (its candidate index)
-      for (uint32_t h = tid; h < n2; h += NT) T2.best[h] = kNone;
-      wg_barrier<RING>();
-      for (uint32_t k = tid; k < nc; k += NT)
-        if (M.cand[k].s < 0.0f) T2.best[M.cand[k].a] = k;
-      wg_barrier<RING>();
     }
 
     // ---- 3. active table: surviving tracks compacted in place, then new seeds ----
+    // Every lane reads its entry before the scan's barrier and writes after it;
+    // entries only move down, and a chunk writes below the entries of later chunks.
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
       const uint32_t t = b0 + tid;
@@ -542,17 +617,15 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         f_tx = A.tx[t]; f_ty = A.ty[t]; f_la = A.la[t]; f_n = A.n[t]; f_skip = A.skip[t];
       }
       uint32_t tot;
-      const uint32_t pos = carry + block_scan<NT, RING>(keep ? 1u : 0u, sc.tmp, &tot);
-      wg_barrier<RING>();  // every entry of this chunk is read before any is overwritten
+      const uint32_t pos = carry + scan(keep ? 1u : 0u, &tot);
       if (keep) {
         A.slot[pos] = f_slot; A.key0[pos] = f_key0; A.xa[pos] = f_xa; A.ya[pos] = f_ya;
         A.tx[pos] = f_tx; A.ty[pos] = f_ty; A.la[pos] = f_la; A.n[pos] = f_n; A.skip[pos] = f_skip;
       }
       carry += tot;
-      wg_barrier<RING>();
     }
     const uint32_t n_keep = carry;
-    if (l <= kLayers - 3) {
+    if (l <= kLayers - 3 && sc.ncs > 0) {
       // seeds in decreasing key of h0 (decreasing local index on plane l+2)
       const uint32_t created = sc.n_created;
       uint32_t c2 = 0;
@@ -560,20 +633,20 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         const uint32_t i0 = b0 + tid < n2 ? n2 - 1 - (b0 + tid) : kNone;
         const uint32_t k = i0 != kNone ? lda(T2.best + i0) : kNone;
         uint32_t tot;
-        const uint32_t rank = c2 + block_scan<NT, RING>(k != kNone ? 1u : 0u, sc.tmp, &tot);
+        const uint32_t rank = c2 + scan(k != kNone ? 1u : 0u, &tot);
         if (k != kNone) {
           const Cand c = M.cand[k];
           const uint32_t slot = (uint32_t)io.slot_base + created + rank;
           uint32_t* hi = io.hit_idx + 26ull * slot;
-          hi[0] = io.lstart[l + 2] + c.a;
-          hi[1] = io.lstart[l + 1] + c.b;
-          hi[2] = base0 + c.c;
+          hi[0] = io.lstart[l + 2] + i0;
+          hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[c.b];
+          hi[2] = base0 + (uint32_t)T0.kr[c.c];
           const uint32_t pos = n_keep + rank;
           if (pos < M.capT) {
             const float x1 = T1.hx[c.b], y1 = T1.hy[c.b], x2 = T0.hx[c.c], y2 = T0.hy[c.c];
             const float dz = zl - zt[l + 1];
             A.slot[pos] = slot;
-            A.key0[pos] = ((uint32_t)(l + 2) << 22) | c.a;
+            A.key0[pos] = ((uint32_t)(l + 2) << 22) | i0;
             A.xa[pos] = x2;
             A.ya[pos] = y2;
             A.tx[pos] = (x2 - x1) / dz;
@@ -588,7 +661,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       n_new = c2;
     }
     if (n_keep + n_new > M.capT) return 1u;
-    if (tid == 0) { sc.n_act = n_keep + n_new; sc.n_created += n_new; }
+    if (tid == 0) { sc.n_act = n_keep + n_new; sc.n_created += n_new; sc.ncf = 0; }
     wg_barrier<RING>();
   }
   // close the tracks still active after the first plane
@@ -600,14 +673,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 // ---------------------------------------------------------------------------
 
 // Azimuth tables of every (event, plane): one 64-lane workgroup per plane,
-// counting sort of the plane's hits by pseudo-angle bucket.  The order inside
-// a bucket is irrelevant: every use scans whole buckets.
+// counting sort of the plane's hits by pseudo-angle bucket; at every bucket
+// position the hit's coordinates and local index.  The order inside a bucket
+// is irrelevant: every use scans whole buckets.
 __global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, const float* __restrict__ Y,
                                                    const uint32_t* __restrict__ hstatus,
                                                    const uint32_t* __restrict__ lstart,
                                                    const uint32_t* __restrict__ lnh,
                                                    const uint64_t* __restrict__ offsets,
                                                    uint64_t n_pixels, uint32_t* __restrict__ order,
+                                                   float* __restrict__ xs, float* __restrict__ ys,
                                                    uint32_t* __restrict__ bst) {
   __shared__ uint32_t cnt[kNB], cur[kNB];
   const uint32_t seg = blockIdx.x, e = seg / kLayers, l = seg % kLayers;
@@ -633,13 +708,16 @@ __global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, 
   if (threadIdx.x == 0) bs[kNB] = carry;
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n; i += 64) {
-    const uint32_t b = bucket_of(pangle(X[base + i], Y[base + i]), kNB);
-    order[base + atomicAdd(cur + b, 1u)] = i;
+    const float x = X[base + i], y = Y[base + i];
+    const uint64_t p = base + atomicAdd(cur + bucket_of(pangle(x, y), kNB), 1u);
+    order[p] = i;
+    xs[p] = x;
+    ys[p] = y;
   }
 }
 
 struct FindArgs {
-  const float* X;  // hit arrays (absolute slots)
+  const float* X;  // hit coordinates in bucket order (absolute slots)
   const float* Y;
   const uint32_t* hstatus;
   const uint32_t* lstart;
@@ -698,7 +776,7 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
                                                  const uint32_t* __restrict__ list_count,
                                                  uint32_t* __restrict__ steal) {
   __shared__ float s_hx[3 * CAPL], s_hy[3 * CAPL];
-  __shared__ uint16_t s_bl[3 * CAPL];
+  __shared__ uint16_t s_kr[3 * CAPL];
   __shared__ uint8_t s_used[3 * CAPL];
   __shared__ uint32_t s_best[3 * CAPL];
   __shared__ uint32_t s_bstart[3 * (kNB + 1)];
@@ -711,7 +789,7 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
   M.w0 = s_w0; M.w1 = s_w1; M.wp = s_wp; M.dbl = s_dbl; M.capD = CAPD;
-  M.hx = s_hx; M.hy = s_hy; M.bl = s_bl; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
+  M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
   M.T = TrackTab{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
   M.cand = s_cand;
   M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
@@ -748,7 +826,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     const uint64_t b = a.offsets[e];
     const uint32_t ne = (uint32_t)(a.offsets[e + 1] - b);
     FindMem<uint32_t, false> M;
-    M.hx = nullptr; M.hy = nullptr; M.bl = nullptr; M.bstart = nullptr;
+    M.hx = nullptr; M.hy = nullptr; M.kr = nullptr; M.bstart = nullptr;
     M.used = g.used + b;
     M.best = g.best + b;
     const uint64_t tb = b / 3;
@@ -781,6 +859,7 @@ static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct FindWs {
   uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *order, *bst;
+  float *xs, *ys;
   GlobalTabs g;
 };
 
@@ -795,6 +874,8 @@ static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, Find
   f.esc2_count = (uint32_t*)take(4);
   f.esc2_list = (uint32_t*)take(4ull * n_events);
   f.order = (uint32_t*)take(4ull * n_pixels);
+  f.xs = (float*)take(4ull * n_pixels);
+  f.ys = (float*)take(4ull * n_pixels);
   f.bst = (uint32_t*)take(4ull * n_events * kLayers * (kNB + 1));
   f.g.best = (uint32_t*)take(4ull * n_pixels);
   f.g.used = (uint8_t*)take(n_pixels);
@@ -845,13 +926,13 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
                            hipStream_t s, const FindCfg& cfg) {
   FindWs f;
   find_ws_layout((char*)ws, n_pixels, n_events, &f);
-  FindArgs a{h->x, h->y, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
+  FindArgs a{f.xs, f.ys, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
              n_pixels, t->n_tracks, t->nhits, t->hit_idx, t->status, f.esc_count, f.esc_list};
   const FindConst c = make_find_const(p);
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc_count, 0u, f.esc_count);
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
   hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
-                     h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.bst);
+                     h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.xs, f.ys, f.bst);
   const bool ws_mode = cfg.small_grid != 0;
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
   const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;

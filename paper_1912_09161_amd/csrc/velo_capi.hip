@@ -53,6 +53,7 @@ velo_status velo_cluster(const uint32_t* d_pixels, const uint64_t* d_offsets, ui
                          uint64_t n_pixels, const velo_hits* out, void* d_ws, size_t ws_bytes,
                          hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(out) || (n_pixels > 0 && !d_pixels) || !d_ws) return VELO_ERR_ARG;
   if (n_pixels >= (1ull << 32) * 3) return VELO_ERR_ARG;
   if (ws_bytes < velo::cluster_workspace_bytes(n_pixels, n_events)) return VELO_ERR_WORKSPACE;
@@ -63,6 +64,7 @@ velo_status velo_find_tracks(const velo_hits* hits, const uint64_t* d_offsets, u
                              uint64_t n_pixels, const velo_params* params, const velo_tracks* out,
                              void* d_ws, size_t ws_bytes, hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(out) || !params_ok(params) || !d_ws)
     return VELO_ERR_ARG;
   if (n_pixels >= (1ull << 32) * 3) return VELO_ERR_ARG;
@@ -74,6 +76,7 @@ velo_status velo_fit(const velo_hits* hits, const velo_tracks* tracks, const uin
                      uint32_t n_events, uint64_t n_pixels, const velo_params* params,
                      const velo_states* out, hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(out) || !params_ok(params))
     return VELO_ERR_ARG;
   return hip_status(velo::launch_fit(hits, tracks, d_offsets, n_events, n_pixels, params, out, stream));
@@ -84,6 +87,7 @@ velo_status velo_reconstruct(const uint32_t* d_pixels, const uint64_t* d_offsets
                              const velo_tracks* tracks, const velo_states* states, void* d_ws,
                              size_t ws_bytes, hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(states) ||
       !params_ok(params) || (n_pixels > 0 && !d_pixels) || !d_ws)
     return VELO_ERR_ARG;
@@ -100,6 +104,7 @@ velo_status velo_fit_mlp(const velo_hits* hits, const velo_tracks* tracks, const
                          uint32_t n_events, uint64_t n_pixels, const velo_params* params,
                          const velo_mlp* mlp, const velo_states* out, hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(out) || !out->score ||
       !params_ok(params) || !mlp_ok(mlp))
     return VELO_ERR_ARG;
@@ -113,6 +118,7 @@ velo_status velo_reconstruct_mlp(const uint32_t* d_pixels, const uint64_t* d_off
                                  const velo_tracks* tracks, const velo_states* states, void* d_ws,
                                  size_t ws_bytes, hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(states) || !states->score ||
       !params_ok(params) || !mlp_ok(mlp) || (n_pixels > 0 && !d_pixels) || !d_ws)
     return VELO_ERR_ARG;
@@ -130,6 +136,7 @@ velo_status velo_track_features(const velo_hits* hits, const velo_tracks* tracks
                                 uint32_t n_events, uint64_t n_pixels, float* d_feat,
                                 hipStream_t stream) {
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(states) || !d_feat)
     return VELO_ERR_ARG;
   return hip_status(velo::launch_features(hits, tracks, states, d_offsets, n_events, n_pixels, d_feat,
@@ -206,6 +213,7 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
                                      hipStream_t stream) {
   if (!ctx) return VELO_ERR_ARG;
   if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(states) ||
       !params_ok(params) || (n_pixels > 0 && !d_pixels) || !d_ws || (mlp && (!mlp_ok(mlp) || !states->score)))
     return VELO_ERR_ARG;

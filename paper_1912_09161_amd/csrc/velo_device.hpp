@@ -89,4 +89,35 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32
   }
 }
 
+// Workgroup exclusive scan with a single barrier: `tmp` (NT/64 words of LDS)
+// must not be reused by the next scan, so callers alternate two buffers (the
+// barrier of the next scan orders the reads of this one before any reuse).
+template <int NT, bool LDS_ONLY = false>
+__device__ __forceinline__ uint32_t block_scan1(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if constexpr (NW == 1) {
+    *total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+  } else {
+    if (lane == kWave - 1) tmp[wid] = x;
+    wg_barrier<LDS_ONLY>();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      uint32_t t = tmp[w];
+      if (w < wid) base += t;
+      tot += t;
+    }
+    *total = tot;
+    return base + x - v;
+  }
+}
+
 }  // namespace velo
