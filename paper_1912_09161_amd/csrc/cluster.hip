@@ -8,10 +8,10 @@
 //   k_validate  one workgroup per event: bad word / hole / plane-order flags
 //               and the plane boundaries (layer_start) of the event
 //   k_small     one 64-lane workgroup per (event, plane) segment of at most
-//               kSmallCap words: LDS counting sort by row, 8-neighbour
-//               union-find within two row buckets (roots = smallest
-//               addresses), integer charge sums, emission at the rank of each
-//               cluster key; larger segments are appended to a work list
+//               kSmallCap words: LDS counting sort by address (row buckets,
+//               then rank inside the row), 8-neighbour union-find (roots =
+//               smallest addresses), integer charge sums, ordered emission by
+//               a prefix count; larger segments are appended to a work list
 //   k_mid       persistent 256-lane workgroups over the work list: the same
 //               algorithm in LDS up to kMidCap words, else in the caller's
 //               workspace at the segment's own word positions
@@ -40,7 +40,8 @@ __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Find the root of x (parent pointers over row-bucket positions).
+// Union-find over address-ordered positions: the root of a tree is its
+// smallest position, i.e. its pixel of smallest address.
 __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
   uint32_t p = ld(par + x);
   while (p != x) {
@@ -50,34 +51,53 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
   return x;
 }
 
-// Join the trees of a and b, hooking the root that is larger in (address,
-// position) order under the smaller one, so that every tree's root is its
-// pixel of smallest address.  The order is strict even for repeated
-// addresses, so no cycle can form.
-__device__ __forceinline__ void uf_unite(uint32_t* par, const uint32_t* srt, uint32_t a, uint32_t b) {
+// Join the trees of a and b by hooking the larger root under the smaller.
+__device__ __forceinline__ void uf_unite(uint32_t* par, uint32_t a, uint32_t b) {
   while (true) {
     a = uf_find(par, a);
     b = uf_find(par, b);
     if (a == b) return;
-    const uint32_t va = ld(srt + a) >> 4, vb = ld(srt + b) >> 4;
-    if (va > vb || (va == vb && a > b)) { uint32_t t = a; a = b; b = t; }
-    if (atomicCAS(par + b, b, a) == b) return;
+    if (a > b) { uint32_t t = a; a = b; b = t; }
+    const uint32_t old = atomicMin(par + b, a);
+    if (old == b) return;
+    b = old;
   }
 }
 
+// Per-row table of one segment.  PACKED (LDS tiers, n <= 65535): two rows
+// per word, 16 bits each; otherwise one word per row.  add() returns the
+// row's previous value.
+template <bool PACKED>
+struct RowTab {
+  uint32_t* w;
+  static constexpr uint32_t kWords = PACKED ? kPix / 2 : kPix;
+  __device__ __forceinline__ uint32_t add(uint32_t r) const {
+    if constexpr (PACKED) {
+      const uint32_t sh = (r & 1u) << 4;
+      return (atomicAdd(w + (r >> 1), 1u << sh) >> sh) & 0xFFFFu;
+    } else {
+      return atomicAdd(w + r, 1u);
+    }
+  }
+  __device__ __forceinline__ uint32_t get(uint32_t r) const {
+    if constexpr (PACKED) return (ld(w + (r >> 1)) >> ((r & 1u) << 4)) & 0xFFFFu;
+    else return ld(w + r);
+  }
+};
+
 // Scratch of one segment of n words (LDS, or the caller's workspace at the
-// segment's own word positions).
+// segment's own word positions).  PACKED: Q and N share one word (Q in the
+// high half; n <= 2048 keeps Q below 2^16).
+template <bool PACKED>
 struct SegScratch {
-  uint32_t* rs;   // [kPix] per-row counts, then bucket starts, then bucket ends
-  uint32_t* srt;  // [n] address << 4 | charge, in row-bucket order
-  uint32_t* par;  // [n] union-find parents (row-bucket positions)
-  uint32_t* qs;   // [n] per root: charge sum
-  uint32_t* ns;   // [n] pixel count
-  uint32_t* scs;  // [n] charge-weighted column sum
-  uint32_t* srs;  // [n] charge-weighted row sum
-  uint32_t* pre;  // [n] roots at earlier positions
-  uint32_t* tmp;  // NT/64 + 1 words of LDS (scans)
-  uint32_t* flag; // one word of LDS
+  uint32_t* rows;  // RowTab words: row counts, then row starts, then row ends
+  uint32_t* srt;   // [n] address << 4 | charge, in address order
+  uint32_t* par;   // [n] bucket-order staging, then union-find parents
+  uint32_t* qs;    // [n] per root: Q << 16 | N (PACKED) or Q
+  uint32_t* ns;    // [n] per root: N (unused when PACKED)
+  uint64_t* scr;   // [n] per root: charge-weighted row sum << 32 | column sum
+  uint32_t* tmp;   // NT/64 + 1 words of LDS (scans)
+  uint32_t* flag;  // one word of LDS
 };
 
 // Cluster the n words of one (event, plane) segment with NT lanes; writes the
@@ -85,113 +105,129 @@ struct SegScratch {
 // segment's keys).  Returns the number of clusters, or kDupBit if two words
 // share an address.
 //
-// Pixels are counting-sorted by row (positions inside a row arbitrary), so
-// the 8-neighbours of a pixel are found in two short row buckets; the
-// union-find roots are the smallest addresses; the rank of a root is the
-// number of roots in earlier rows (a prefix over positions, which are row
-// major) plus the roots of its own row with a smaller column.
-template <int NT>
+// The pixels are sorted by address with two counting passes: by row into
+// row buckets, then each pixel's rank among the smaller columns of its row
+// bucket.  In address order the same-row neighbour is the next position and
+// the next-row neighbours are a short run of the next row's bucket; the
+// union-find roots are the smallest positions (= addresses), so the roots in
+// position order are the clusters in key order and their ranks are a prefix
+// count.
+template <int NT, bool PACKED>
 __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, uint32_t layer,
-                                    const SegScratch& S, HitsOut o, uint64_t out_base) {
-  constexpr uint32_t RPL = (kPix + NT - 1) / NT;  // rows per lane in the row scan
+                                    const SegScratch<PACKED>& S, HitsOut o, uint64_t out_base) {
+  constexpr uint32_t WPL = (RowTab<PACKED>::kWords + NT - 1) / NT;  // row words per lane
   const uint32_t tid = threadIdx.x;
-  uint32_t* rs = S.rs;
-  for (uint32_t r = tid; r < (uint32_t)kPix; r += NT) rs[r] = 0;
+  const RowTab<PACKED> rt{S.rows};
+  for (uint32_t i = tid; i < RowTab<PACKED>::kWords; i += NT) S.rows[i] = 0;
   if (tid == 0) *S.flag = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += NT) atomicAdd(rs + w_row(w[i]), 1u);
+  for (uint32_t i = tid; i < n; i += NT) rt.add(w_row(w[i]));
   __syncthreads();
-  {  // bucket starts: exclusive prefix over rows, RPL consecutive rows per lane
-    const uint32_t r0 = tid * RPL;
-    uint32_t c[RPL], sum = 0;
+  {  // row starts: exclusive prefix over rows, WPL consecutive words per lane
+    const uint32_t w0 = tid * WPL;
+    uint32_t c[WPL], sum = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < RPL; ++k) {
-      c[k] = r0 + k < (uint32_t)kPix ? ld(rs + r0 + k) : 0u;
-      sum += c[k];
+    for (uint32_t k = 0; k < WPL; ++k) {
+      c[k] = w0 + k < RowTab<PACKED>::kWords ? ld(S.rows + w0 + k) : 0u;
+      sum += PACKED ? (c[k] & 0xFFFFu) + (c[k] >> 16) : c[k];
     }
     uint32_t tot;
     uint32_t run = block_scan<NT>(sum, S.tmp, &tot);
 #pragma unroll
-    for (uint32_t k = 0; k < RPL; ++k) {
-      if (r0 + k < (uint32_t)kPix) rs[r0 + k] = run;
-      run += c[k];
-    }
-  }
-  __syncthreads();
-  // scatter into row buckets (afterwards rs[r] = end of bucket r)
-  for (uint32_t i = tid; i < n; i += NT) {
-    const uint32_t v = w[i];
-    const uint32_t p = atomicAdd(rs + w_row(v), 1u);
-    S.srt[p] = ((w_row(v) << 11 | w_col(v)) << 4) | w_charge(v);
-  }
-  for (uint32_t p = tid; p < n; p += NT) {
-    S.par[p] = p;
-    S.qs[p] = 0;
-    S.ns[p] = 0;
-    S.scs[p] = 0;
-    S.srs[p] = 0;
-  }
-  __syncthreads();
-  // repeated addresses, and edges to (r, c+1), (r+1, c-1..c+1)
-  bool dup = false;
-  for (uint32_t p = tid; p < n; p += NT) {
-    const uint32_t a = ld(S.srt + p) >> 4;
-    const uint32_t r = a >> 11, c = a & 0x7FFu;
-    const uint32_t b0 = r ? ld(rs + r - 1) : 0u, b1 = ld(rs + r);
-    for (uint32_t q = b0; q < b1; ++q) {
-      const uint32_t aq = ld(S.srt + q) >> 4;
-      if (q != p && aq == a) dup = true;
-      if (aq == a + 1) uf_unite(S.par, S.srt, p, q);
-    }
-    if (r + 1 < (uint32_t)kPix) {
-      const uint32_t e1 = ld(rs + r + 1);
-      for (uint32_t q = b1; q < e1; ++q) {
-        const uint32_t cq = (ld(S.srt + q) >> 4) & 0x7FFu;
-        if (cq + 1 >= c && cq <= c + 1) uf_unite(S.par, S.srt, p, q);
+    for (uint32_t k = 0; k < WPL; ++k) {
+      if (w0 + k >= RowTab<PACKED>::kWords) continue;
+      if constexpr (PACKED) {
+        const uint32_t lo = run, hi = run + (c[k] & 0xFFFFu);
+        S.rows[w0 + k] = lo | (hi << 16);
+        run = hi + (c[k] >> 16);
+      } else {
+        S.rows[w0 + k] = run;
+        run += c[k];
       }
     }
+  }
+  __syncthreads();
+  // row buckets (staged in par); afterwards the table holds the row ends
+  for (uint32_t i = tid; i < n; i += NT) {
+    const uint32_t v = w[i];
+    S.par[rt.add(w_row(v))] = ((w_row(v) << 11 | w_col(v)) << 4) | w_charge(v);
+  }
+  __syncthreads();
+  // address order: row start + smaller columns in the row; equal columns are
+  // repeated addresses
+  bool dup = false;
+  for (uint32_t p = tid; p < n; p += NT) {
+    const uint32_t v = ld(S.par + p);
+    const uint32_t r = (v >> 15) & 0x7FFu, c = (v >> 4) & 0x7FFu;
+    const uint32_t b0 = r ? rt.get(r - 1) : 0u, b1 = rt.get(r);
+    uint32_t k = b0;
+    for (uint32_t q = b0; q < b1; ++q) {
+      const uint32_t cq = (ld(S.par + q) >> 4) & 0x7FFu;
+      k += cq < c;
+      dup |= q != p && cq == c;
+    }
+    S.srt[k] = v;
   }
   if (dup) atomicOr(S.flag, 1u);
   __syncthreads();
   if (ld(S.flag)) return kDupBit;
+  for (uint32_t p = tid; p < n; p += NT) {
+    S.par[p] = p;
+    S.qs[p] = 0;
+    if constexpr (!PACKED) S.ns[p] = 0;
+    S.scr[p] = 0;
+  }
+  __syncthreads();
+  // edges to (r, c+1) and (r+1, c-1..c+1)
+  for (uint32_t p = tid; p < n; p += NT) {
+    const uint32_t a = ld(S.srt + p) >> 4;
+    const uint32_t r = a >> 11, c = a & 0x7FFu;
+    if (p + 1 < n && (ld(S.srt + p + 1) >> 4) == a + 1) uf_unite(S.par, p, p + 1);
+    if (r + 1 < (uint32_t)kPix) {
+      const uint32_t e1 = rt.get(r + 1);
+      for (uint32_t q = rt.get(r); q < e1; ++q) {
+        const uint32_t cq = (ld(S.srt + q) >> 4) & 0x7FFu;
+        if (cq > c + 1) break;
+        if (cq + 1 >= c) uf_unite(S.par, p, q);
+      }
+    }
+  }
+  __syncthreads();
   // integer sums at the roots
   for (uint32_t p = tid; p < n; p += NT) {
     const uint32_t r = uf_find(S.par, p);
     const uint32_t v = ld(S.srt + p);
     const uint32_t q = v & 15u, a = v >> 4;
-    atomicAdd(S.qs + r, q);
-    atomicAdd(S.ns + r, 1u);
-    atomicAdd(S.scs + r, q * (a & 0x7FFu));
-    atomicAdd(S.srs + r, q * (a >> 11));
+    if constexpr (PACKED) {
+      atomicAdd(S.qs + r, (q << 16) | 1u);
+    } else {
+      atomicAdd(S.qs + r, q);
+      atomicAdd(S.ns + r, 1u);
+    }
+    atomicAdd((unsigned long long*)(S.scr + r),
+              ((unsigned long long)(q * (a >> 11)) << 32) | (unsigned long long)(q * (a & 0x7FFu)));
     if (r != p) S.par[p] = r;
   }
   __syncthreads();
-  // roots at earlier positions
+  // roots in position order = clusters in key order
   uint32_t carry = 0;
   for (uint32_t b = 0; b < n; b += NT) {
     const uint32_t p = b + tid;
     const bool root = p < n && ld(S.par + p) == p;
     uint32_t tot;
-    const uint32_t ex = block_scan<NT>(root ? 1u : 0u, S.tmp, &tot);
-    if (p < n) S.pre[p] = carry + ex;
+    const uint32_t rank = block_scan<NT>(root ? 1u : 0u, S.tmp, &tot);
+    if (root) {
+      const uint64_t slot = out_base + carry + rank;
+      const uint32_t qv = ld(S.qs + p);
+      const uint32_t Q = PACKED ? qv >> 16 : qv, N = PACKED ? qv & 0xFFFFu : ld(S.ns + p);
+      const uint64_t sr = S.scr[p];
+      const uint32_t SC = (uint32_t)sr, SR = (uint32_t)(sr >> 32);
+      o.x[slot] = ((float)SC / (float)Q - 767.5f) * 0.055f;
+      o.y[slot] = ((float)SR / (float)Q - 767.5f) * 0.055f;
+      o.key[slot] = (layer << 22) | (ld(S.srt + p) >> 4);
+      o.aux[slot] = ((N < 65535u ? N : 65535u) << 16) | (Q < 65535u ? Q : 65535u);
+    }
     carry += tot;
-  }
-  __syncthreads();
-  // rank and emission
-  for (uint32_t p = tid; p < n; p += NT) {
-    if (ld(S.par + p) != p) continue;
-    const uint32_t a = ld(S.srt + p) >> 4;
-    const uint32_t r = a >> 11, c = a & 0x7FFu;
-    const uint32_t b0 = r ? ld(rs + r - 1) : 0u, b1 = ld(rs + r);
-    uint32_t rank = ld(S.pre + b0);
-    for (uint32_t q = b0; q < b1; ++q)
-      if (ld(S.par + q) == q && ((ld(S.srt + q) >> 4) & 0x7FFu) < c) ++rank;
-    const uint64_t slot = out_base + rank;
-    const uint32_t Q = ld(S.qs + p), N = ld(S.ns + p), SC = ld(S.scs + p), SR = ld(S.srs + p);
-    o.x[slot] = ((float)SC / (float)Q - 767.5f) * 0.055f;
-    o.y[slot] = ((float)SR / (float)Q - 767.5f) * 0.055f;
-    o.key[slot] = (layer << 22) | a;
-    o.aux[slot] = ((N < 65535u ? N : 65535u) << 16) | (Q < 65535u ? Q : 65535u);
   }
   return carry;
 }
@@ -278,12 +314,12 @@ struct SmallArgs {
 };
 
 struct SmallLds {
-  uint32_t rs[kPix];
-  uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap], ns[kSmallCap], scs[kSmallCap],
-      srs[kSmallCap], pre[kSmallCap];
+  uint32_t rows[kPix / 2];
+  uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap];
+  uint64_t scr[kSmallCap];
   uint32_t tmp[2], flag;
-  __device__ SegScratch scratch() {
-    return SegScratch{rs, srt, par, qs, ns, scs, srs, pre, tmp, &flag};
+  __device__ SegScratch<true> scratch() {
+    return SegScratch<true>{rows, srt, par, qs, nullptr, scr, tmp, &flag};
   }
 };
 
@@ -304,7 +340,7 @@ __device__ __forceinline__ void small_segment(const SmallArgs& a, SmallLds& S, u
   }
   uint32_t cnt = 0;
   if (n > 0)
-    cnt = cluster_segment<64>(a.px + b + s0, n, l, S.scratch(), a.o, b + s0);
+    cnt = cluster_segment<64, true>(a.px + b + s0, n, l, S.scratch(), a.o, b + s0);
   if (threadIdx.x == 0) a.layer_nhits[seg] = cnt;
 }
 
@@ -340,10 +376,11 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ layer_nhits, HitsOut o,
                                                      const uint32_t* __restrict__ mid_count,
                                                      const uint32_t* __restrict__ mid_list,
-                                                     uint32_t* __restrict__ ws, uint64_t n_pixels,
+                                                     uint32_t* __restrict__ ws,
+                                                     uint64_t* __restrict__ ws64, uint64_t n_pixels,
                                                      uint32_t* __restrict__ steal) {
-  __shared__ uint32_t rs[kPix], srt[kMidCap], par[kMidCap], qs[kMidCap], ns[kMidCap],
-      scs[kMidCap], srs[kMidCap], pre[kMidCap];
+  __shared__ uint32_t rows[kPix / 2], srt[kMidCap], par[kMidCap], qs[kMidCap];
+  __shared__ uint64_t scr[kMidCap];
   __shared__ uint32_t tmp[kMidThreads / kWave + 1], flag, item;
   const uint32_t count = *mid_count;
   // static round robin, or work stealing from a counter when `steal` is given
@@ -356,16 +393,16 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
     const uint32_t n = s1 - s0;
     uint32_t cnt;
     if (n <= kMidCap) {
-      const SegScratch S{rs, srt, par, qs, ns, scs, srs, pre, tmp, &flag};
-      cnt = cluster_segment<kMidThreads>(px + b + s0, n, l, S, o, b + s0);
+      const SegScratch<true> S{rows, srt, par, qs, nullptr, scr, tmp, &flag};
+      cnt = cluster_segment<kMidThreads, true>(px + b + s0, n, l, S, o, b + s0);
     } else {
       // scratch in the workspace at the segment's own word positions (n > kPix,
       // so the row table fits there too)
       const uint64_t p0 = b + s0;
-      const SegScratch S{ws + p0, ws + n_pixels + p0, ws + 2 * n_pixels + p0, ws + 3 * n_pixels + p0,
-                         ws + 4 * n_pixels + p0, ws + 5 * n_pixels + p0, ws + 6 * n_pixels + p0,
-                         ws + 7 * n_pixels + p0, tmp, &flag};
-      cnt = cluster_segment<kMidThreads>(px + p0, n, l, S, o, p0);
+      const SegScratch<false> S{ws + p0, ws + n_pixels + p0, ws + 2 * n_pixels + p0,
+                                ws + 3 * n_pixels + p0, ws + 4 * n_pixels + p0,
+                                ws64 + p0, tmp, &flag};
+      cnt = cluster_segment<kMidThreads, false>(px + p0, n, l, S, o, p0);
     }
     if (threadIdx.x == 0) layer_nhits[seg] = cnt;
     __syncthreads();
@@ -411,7 +448,7 @@ struct ClusterCfg {
 
 size_t cluster_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-  return up(4) + up(4ull * kLayers * n_events) + up(8ull * 4 * n_pixels);
+  return up(4) + up(4ull * kLayers * n_events) + up(5ull * 4 * n_pixels) + up(8ull * n_pixels);
 }
 
 hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
@@ -422,6 +459,7 @@ hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint3
   uint32_t* mid_count = (uint32_t*)base;
   uint32_t* mid_list = (uint32_t*)(base + up(4));
   uint32_t* scratch = (uint32_t*)(base + up(4) + up(4ull * kLayers * n_events));
+  uint64_t* scratch64 = (uint64_t*)((char*)scratch + up(5ull * 4 * n_pixels));
   HitsOut o{h->x, h->y, h->key, h->aux};
   if (!validated) {
     hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
@@ -436,7 +474,7 @@ hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint3
     hipLaunchKernelGGL(k_small_ws, dim3(cfg.small_grid), dim3(64), 0, s, a, cfg.seg_order,
                        n_events * kLayers, cfg.counters);
   hipLaunchKernelGGL(k_mid, dim3(cfg.mid_grid), dim3(kMidThreads), 0, s, px, offsets, h->layer_start,
-                     h->layer_nhits, o, mid_count, mid_list, scratch, n_pixels,
+                     h->layer_nhits, o, mid_count, mid_list, scratch, scratch64, n_pixels,
                      cfg.small_grid ? cfg.counters + 1 : (uint32_t*)nullptr);
   hipLaunchKernelGGL(k_finalize, dim3((n_events + 255) / 256), dim3(256), 0, s, offsets, n_events,
                      n_pixels, h->status, h->layer_start, h->layer_nhits, h->n_hits);

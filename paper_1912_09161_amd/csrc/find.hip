@@ -42,7 +42,7 @@ struct FindConst {
   float rho_seed, rho_fwd;  // upper bounds of sqrt(s_seed), sqrt(s_fwd)
 };
 
-constexpr uint32_t kNB = 64;  // azimuth buckets per plane
+constexpr uint32_t kNB = 256;  // azimuth buckets per plane
 
 // One plane, indexed by bucket position p.  The hit's local index (rank of
 // its key in the plane, the order of its event-relative slot) is kr[p].
@@ -451,15 +451,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         });
       };
       // doublet cuts of (h0 on l+2, h1 on l+1); returns false if rejected
+      // (the division-free azimuth cuts first: most pairs fail them)
       auto doublet = [&](float x0, float y0, float x1, float y1, float& tx, float& ty) {
-        tx = (x1 - x0) / dz01;
-        ty = (y1 - y0) / dz01;
-        if (!(fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t)) return false;
         const float cr = x0 * y1 - y0 * x1;
         const float r0s = x0 * x0 + y0 * y0;
         const float r1s = x1 * x1 + y1 * y1;
         if (!(cr * cr <= (P.sin2 * r0s) * r1s)) return false;
-        return x0 * x1 + y0 * y1 > 0.0f;
+        if (!(x0 * x1 + y0 * y1 > 0.0f)) return false;
+        tx = (x1 - x0) / dz01;
+        ty = (y1 - y0) / dz01;
+        return fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t;
       };
       if constexpr (RING) {
         // (a) window of every unused middle hit on plane l+2, prefix of the sizes
