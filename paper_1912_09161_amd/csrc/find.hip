@@ -46,19 +46,20 @@ constexpr uint32_t kNB = 256;  // azimuth buckets per plane
 
 // One plane, indexed by bucket position p.  The hit's local index (rank of
 // its key in the plane, the order of its event-relative slot) is kr[p].
-template <typename IDX>
+template <typename IDX, typename SLOT>
 struct LayerTab {
   const float* hx;
   const float* hy;
   const IDX* kr;          // local index of the hit at each position
   uint8_t* used;
-  uint32_t* best;         // candidate holding the hit in a round
+  SLOT* best;             // round winner at the hit (see Cands)
   const uint32_t* bstart; // [kNB + 1] first position of every bucket
 };
 
+template <typename SLOT>
 struct TrackTab {
   uint32_t* slot;   // output slot
-  uint32_t* key0;   // first hit: plane << 22 | local index (orders like its key)
+  uint32_t* key0;   // first hit: plane << KSH | local index (orders like its key)
   float* xa;        // last hit
   float* ya;
   float* tx;        // slope through the last two hits
@@ -66,14 +67,27 @@ struct TrackTab {
   uint8_t* la;      // plane of the last hit
   uint8_t* n;       // hits so far
   uint8_t* skip;    // planes missed in a row
-  uint32_t* tbest;  // per round: best candidate of the track
+  SLOT* tbest;      // per round: winner at the track
   uint32_t* tmatch; // position of the hit taken at this plane
 };
 
+// Candidates.  Extension: track a, hit b; seed: h0 a, h1 b, h2 c (bucket
+// positions).  Priority: extension (s, first-hit key of the track, hit key),
+// seed (s, key of h1, key of h0, key of h2); s >= 0, so its float bits order
+// like s.
+//   LDS tiers (local indices < 1024): the priority packed in 64 bits, unique
+//   per candidate; a resource's round winner is the atomic minimum of the
+//   priorities proposed to it.  Positions packed 10 bits each in `pos`, bit 31
+//   marks an accepted seed.
+//   Workspace tier (keys of any width): {s, a, b, c}; the winner slot holds a
+//   candidate index, updated by a CAS loop with a comparator.
 struct Cand {
   float s;
-  uint32_t a, b, c;  // extension: track, hit; seed: h0, h1, h2 (bucket positions)
+  uint32_t a, b, c;
 };
+template <bool RING> struct CandSlot { using T = uint32_t; static constexpr uint32_t kFree = 0xFFFFFFFFu; };
+template <> struct CandSlot<true> { using T = uint64_t; static constexpr uint64_t kFree = ~0ull; };
+constexpr uint32_t kPosBits = 10, kPosMask = (1u << kPosBits) - 1u, kAccepted = 1u << 31;
 
 struct Dbl {
   uint32_t i01;  // h0 | h1 << 16 (bucket positions)
@@ -99,14 +113,18 @@ struct EventIO {
 // in scratch at the plane's own event-relative slots.
 template <typename IDX, bool RING>
 struct FindMem {
+  using SLOT = typename CandSlot<RING>::T;
+  static constexpr uint32_t KSH = RING ? kPosBits : 22;  // key0 = plane << KSH | local index
   float* hx;
   float* hy;
   IDX* kr;
   uint8_t* used;
-  uint32_t* best;
+  SLOT* best;
   uint32_t* bstart;  // [3 * (kNB + 1)]
-  TrackTab T;
-  Cand* cand;
+  TrackTab<SLOT> T;
+  Cand* cand;        // workspace tier
+  uint64_t* cprio;   // LDS tiers
+  uint32_t* cpos;
   // seed doublet search (LDS tiers): per middle hit the two bucket ranges of
   // its window on plane l+2 (start | length << 16) and the prefix of their
   // lengths; passing doublets
@@ -115,13 +133,13 @@ struct FindMem {
   uint32_t* wp;   // [capL + 1]
   Dbl* dbl;       // [capD]
   uint32_t capL, capT, capC, capD;
-  __device__ __forceinline__ LayerTab<IDX> layer(const EventIO& io, int l) const {
+  __device__ __forceinline__ LayerTab<IDX, SLOT> layer(const EventIO& io, int l) const {
     if constexpr (RING) {
       const uint32_t r = (uint32_t)l % 3u, o = r * capL;
-      return LayerTab<IDX>{hx + o, hy + o, kr + o, used + o, best + o, bstart + r * (kNB + 1)};
+      return LayerTab<IDX, SLOT>{hx + o, hy + o, kr + o, used + o, best + o, bstart + r * (kNB + 1)};
     } else {
       const uint32_t o = io.lstart[l];
-      return LayerTab<IDX>{io.X + o, io.Y + o, io.order + o, used + o, best + o,
+      return LayerTab<IDX, SLOT>{io.X + o, io.Y + o, io.order + o, used + o, best + o,
                            io.bst + (uint32_t)l * (kNB + 1)};
     }
   }
@@ -132,7 +150,9 @@ struct FindMem {
 // contained in the pseudo-angle window of the same half width.
 __device__ __forceinline__ float pangle(float x, float y) {
   float ax = fabsf(x), ay = fabsf(y), d = ax + ay;
-  float r = d > 0.0f ? ay / d : 0.0f;
+  // hardware reciprocal (about 1 ulp): bucket assignment and window centres use
+  // this same function, and every window carries a margin far above its error
+  float r = d > 0.0f ? ay * __builtin_amdgcn_rcpf(d) : 0.0f;
   if (y >= 0.0f) return x >= 0.0f ? r : 2.0f - r;
   return x < 0.0f ? 2.0f + r : 4.0f - r;
 }
@@ -164,13 +184,13 @@ __device__ __forceinline__ Ranges window(float c, float d, uint32_t nb) {
   return r;
 }
 
-// pseudo-angle half width for hits within rho of the point (x, y)
+// pseudo-angle half width for hits within rho of the point (x, y) at radius
+// R: the azimuth moves by at most asin(rho / R) <= rho / sqrt(R^2 - rho^2);
+// hardware reciprocal square root (about 1 ulp) under a 0.1 % + 1e-3 margin
 __device__ __forceinline__ float point_window(float x, float y, float rho) {
-  float R2 = x * x + y * y;
-  float rr = 2.25f * rho * rho;  // R <= 1.5 rho: whole plane
-  if (R2 <= rr) return 4.0f;
-  float u2 = (rho * rho) / R2;   // sin^2 of the largest angle
-  return sqrtf(u2 / (1.0f - u2)) * 1.001f + 1e-3f;
+  const float R2 = x * x + y * y, rho2 = rho * rho;
+  if (R2 <= 2.25f * rho2) return 4.0f;  // R <= 1.5 rho: whole plane
+  return rho * __builtin_amdgcn_rsqf(R2 - rho2) * 1.001f + 1e-3f;
 }
 
 template <typename F>
@@ -231,7 +251,7 @@ struct PlanePrefetch {
   template <typename MEM>
   __device__ __forceinline__ void commit(const EventIO& io, int l, const MEM& M) {
     const uint32_t n = io.lnh[l];
-    const LayerTab<IDX> t = M.layer(io, l);
+    const auto t = M.layer(io, l);
     if constexpr (RING) {
       float* hx = const_cast<float*>(t.hx);
       float* hy = const_cast<float*>(t.hy);
@@ -240,7 +260,9 @@ struct PlanePrefetch {
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; t.used[i] = 0; t.best[i] = kNone; }
+        if (i < n) {
+          hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; t.used[i] = 0; t.best[i] = CandSlot<RING>::kFree;
+        }
       }
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
@@ -248,7 +270,7 @@ struct PlanePrefetch {
         if (b <= kNB) bsd[b] = bs[k];
       }
     } else {
-      for (uint32_t i = threadIdx.x; i < n; i += NT) { t.used[i] = 0; t.best[i] = kNone; }
+      for (uint32_t i = threadIdx.x; i < n; i += NT) { t.used[i] = 0; t.best[i] = CandSlot<RING>::kFree; }
     }
     wg_barrier<RING>();
   }
@@ -256,8 +278,8 @@ struct PlanePrefetch {
 
 // Visit positions [p, e) four at a time: the coordinates of a group are
 // loaded together (clamped to e - 1), so their LDS latencies overlap.
-template <typename IDX, typename F>
-__device__ __forceinline__ void scan_range(const LayerTab<IDX>& t, uint32_t p, uint32_t e, F f) {
+template <typename LT, typename F>
+__device__ __forceinline__ void scan_range(const LT& t, uint32_t p, uint32_t e, F f) {
   for (; p < e; p += 4) {
     float x[4], y[4];
 #pragma unroll
@@ -272,8 +294,8 @@ __device__ __forceinline__ void scan_range(const LayerTab<IDX>& t, uint32_t p, u
   }
 }
 
-template <typename IDX, typename F>
-__device__ __forceinline__ void scan_window(const LayerTab<IDX>& t, Ranges r, F f) {
+template <typename LT, typename F>
+__device__ __forceinline__ void scan_window(const LT& t, Ranges r, F f) {
   scan_range(t, t.bstart[r.b0], t.bstart[r.b1 + 1], f);
   if (r.b2 <= r.b3) scan_range(t, t.bstart[r.b2], t.bstart[r.b3 + 1], f);
 }
@@ -322,11 +344,18 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
   PlanePrefetch<NT, IDX, RING> pf;
   pf.issue(io, kLayers - 1, M.capL);
   wg_barrier<RING>();
-  const TrackTab A = M.T;
+  const auto A = M.T;
+  using SLOT = typename CandSlot<RING>::T;
+  constexpr SLOT kFree = CandSlot<RING>::kFree;
+  // a resource proposes / holds candidate k
+  auto holds = [&](SLOT* slot, uint32_t k) {
+    if constexpr (RING) return __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == M.cprio[k];
+    else return lda(slot) == k;
+  };
   for (int l = kLayers - 1; l >= 0; --l) {
     pf.commit(io, l, M);
     if (l > 0) pf.issue(io, l - 1, M.capL);
-    const LayerTab<IDX> T0 = M.layer(io, l);
+    const auto T0 = M.layer(io, l);
     const uint32_t n0 = io.lnh[l], base0 = io.lstart[l];
     const float zl = zt[l];
     const uint32_t n_act = sc.n_act;
@@ -336,7 +365,8 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     if (tid == 0) { sc.ncs = 0; sc.nd = 0; }
     for (uint32_t t = tid; t < n_act; t += NT) {
       A.tmatch[t] = kNone;
-      A.tbest[t] = kNone;
+      A.tbest[t] = kFree;
+      const uint32_t key0 = A.key0[t];
       const float xa = A.xa[t], ya = A.ya[t], txf = A.tx[t], tyf = A.ty[t];
       const float za = zt[A.la[t]];
       const float d = zl - za;
@@ -348,7 +378,15 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         float s = dx * dx + dy * dy;
         if (s <= P.s_fwd) {
           uint32_t k = atomicAdd(&sc.ncf, 1u);
-          if (k < M.capC) M.cand[k] = Cand{s, t, h, 0u};
+          if (k < M.capC) {
+            if constexpr (RING) {
+              M.cprio[k] = ((uint64_t)__float_as_uint(s) << 32) | ((uint64_t)key0 << kPosBits) |
+                           (uint64_t)T0.kr[h];
+              M.cpos[k] = t | (h << kPosBits);
+            } else {
+              M.cand[k] = Cand{s, t, h, 0u};
+            }
+          }
         }
       });
     }
@@ -369,34 +407,47 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           if (ci.s != cj.s) return ci.s < cj.s;
           return T0.kr[ci.b] < T0.kr[cj.b];
         };
-        auto live = [&](const Cand& c) { return A.tmatch[c.a] == kNone && !T0.used[c.b]; };
+        // (track, hit) of candidate k
+        auto th = [&](uint32_t k, uint32_t& t, uint32_t& h) {
+          if constexpr (RING) { const uint32_t v = M.cpos[k]; t = v & kPosMask; h = v >> kPosBits; }
+          else { const Cand c = M.cand[k]; t = c.a; h = c.b; }
+        };
+        auto live = [&](uint32_t t, uint32_t h) { return A.tmatch[t] == kNone && !T0.used[h]; };
         greedy_rounds<RING>(
             nc, sc,
             [&] {
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                if (live(c)) {
-                  cas_min(T0.best + c.b, k, less_hit);
-                  cas_min(A.tbest + c.a, k, less_trk);
+                uint32_t t, h;
+                th(k, t, h);
+                if (!live(t, h)) continue;
+                if constexpr (RING) {
+                  const uint64_t pr = M.cprio[k];
+                  atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)pr);
+                  atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)pr);
+                } else {
+                  cas_min(T0.best + h, k, less_hit);
+                  cas_min(A.tbest + t, k, less_trk);
                 }
               }
             },
             [&] {
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                if (live(c) && lda(T0.best + c.b) == k && lda(A.tbest + c.a) == k) {
-                  A.tmatch[c.a] = c.b;
-                  T0.used[c.b] = 1;
+                uint32_t t, h;
+                th(k, t, h);
+                if (live(t, h) && holds(T0.best + h, k) && holds(A.tbest + t, k)) {
+                  A.tmatch[t] = h;
+                  T0.used[h] = 1;
                 }
               }
             },
             [&] {
               bool any = false;
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                T0.best[c.b] = kNone;
-                A.tbest[c.a] = kNone;
-                if (live(c)) any = true;
+                uint32_t t, h;
+                th(k, t, h);
+                T0.best[h] = kFree;
+                A.tbest[t] = kFree;
+                if (live(t, h)) any = true;
               }
               return any;
             });
@@ -427,8 +478,8 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 
     // ---- 2. seeds on planes (l+2, l+1, l) ----
     uint32_t n_new = 0;
-    const LayerTab<IDX> T1 = M.layer(io, l < kLayers - 1 ? l + 1 : l);
-    const LayerTab<IDX> T2 = M.layer(io, l < kLayers - 2 ? l + 2 : l);
+    const auto T1 = M.layer(io, l < kLayers - 1 ? l + 1 : l);
+    const auto T2 = M.layer(io, l < kLayers - 2 ? l + 2 : l);
     uint32_t n1 = 0, n2 = 0;
     if (l <= kLayers - 3) {
       n1 = io.lnh[l + 1];
@@ -446,7 +497,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           const float s = dx * dx + dy * dy;
           if (s <= P.s_seed && !T0.used[i2]) {
             uint32_t k = atomicAdd(&sc.ncs, 1u);
-            if (k < M.capC) M.cand[k] = Cand{s, i0, i1, i2};
+            if (k < M.capC) {
+              if constexpr (RING) {
+                M.cprio[k] = ((uint64_t)__float_as_uint(s) << 32) |
+                             ((uint64_t)T1.kr[i1] << (2 * kPosBits)) |
+                             ((uint64_t)T2.kr[i0] << kPosBits) | (uint64_t)T0.kr[i2];
+                M.cpos[k] = i0 | (i1 << kPosBits) | (i2 << (2 * kPosBits));
+              } else {
+                M.cand[k] = Cand{s, i0, i1, i2};
+              }
+            }
           }
         });
       };
@@ -559,46 +619,73 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           if (ci.a != cj.a) return T2.kr[ci.a] < T2.kr[cj.a];
           return T0.kr[ci.c] < T0.kr[cj.c];
         };
-        auto alive = [&](const Cand& c) { return !T2.used[c.a] && !T1.used[c.b] && !T0.used[c.c]; };
+        // hits (h0, h1, h2) of candidate k
+        auto hits3 = [&](uint32_t k, uint32_t& i0, uint32_t& i1, uint32_t& i2) {
+          if constexpr (RING) {
+            const uint32_t v = M.cpos[k];
+            i0 = v & kPosMask; i1 = (v >> kPosBits) & kPosMask; i2 = (v >> (2 * kPosBits)) & kPosMask;
+          } else {
+            const Cand c = M.cand[k]; i0 = c.a; i1 = c.b; i2 = c.c;
+          }
+        };
+        auto alive = [&](uint32_t i0, uint32_t i1, uint32_t i2) {
+          return !T2.used[i0] && !T1.used[i1] && !T0.used[i2];
+        };
         greedy_rounds<RING>(
             nc, sc,
             [&] {
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                if (alive(c)) {
-                  cas_min(T2.best + c.a, k, less_seed);
-                  cas_min(T1.best + c.b, k, less_seed);
-                  cas_min(T0.best + c.c, k, less_seed);
+                uint32_t i0, i1, i2;
+                hits3(k, i0, i1, i2);
+                if (!alive(i0, i1, i2)) continue;
+                if constexpr (RING) {
+                  const unsigned long long pr = M.cprio[k];
+                  atomicMin((unsigned long long*)(T2.best + i0), pr);
+                  atomicMin((unsigned long long*)(T1.best + i1), pr);
+                  atomicMin((unsigned long long*)(T0.best + i2), pr);
+                } else {
+                  cas_min(T2.best + i0, k, less_seed);
+                  cas_min(T1.best + i1, k, less_seed);
+                  cas_min(T0.best + i2, k, less_seed);
                 }
               }
             },
             [&] {
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                if (alive(c) && lda(T2.best + c.a) == k && lda(T1.best + c.b) == k &&
-                    lda(T0.best + c.c) == k) {
-                  T2.used[c.a] = 1;
-                  T1.used[c.b] = 1;
-                  T0.used[c.c] = 1;
-                  M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
+                uint32_t i0, i1, i2;
+                hits3(k, i0, i1, i2);
+                if (alive(i0, i1, i2) && holds(T2.best + i0, k) && holds(T1.best + i1, k) &&
+                    holds(T0.best + i2, k)) {
+                  T2.used[i0] = 1;
+                  T1.used[i1] = 1;
+                  T0.used[i2] = 1;
+                  if constexpr (RING) M.cpos[k] |= kAccepted;
+                  else M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
                 }
               }
             },
             [&] {
               bool any = false;
               for (uint32_t k = tid; k < nc; k += NT) {
-                const Cand c = M.cand[k];
-                T2.best[c.a] = kNone;
-                T1.best[c.b] = kNone;
-                T0.best[c.c] = kNone;
-                if (alive(c)) any = true;
+                uint32_t i0, i1, i2;
+                hits3(k, i0, i1, i2);
+                T2.best[i0] = kFree;
+                T1.best[i1] = kFree;
+                T0.best[i2] = kFree;
+                if (alive(i0, i1, i2)) any = true;
               }
               return any;
             });
         // accepted seed of each h0, stored by the local index of h0 (the slots
         // are clear; nothing reads plane l+2 by position any more)
-        for (uint32_t k = tid; k < nc; k += NT)
-          if (M.cand[k].s < 0.0f) T2.best[T2.kr[M.cand[k].a]] = k;
+        for (uint32_t k = tid; k < nc; k += NT) {
+          uint32_t i0, i1, i2;
+          hits3(k, i0, i1, i2);
+          bool acc;
+          if constexpr (RING) acc = (M.cpos[k] & kAccepted) != 0;
+          else acc = M.cand[k].s < 0.0f;
+          if (acc) T2.best[T2.kr[i0]] = (SLOT)k;
+        }
         wg_barrier<RING>();
       }
     }
@@ -632,22 +719,30 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       uint32_t c2 = 0;
       for (uint32_t b0 = 0; b0 < n2; b0 += NT) {
         const uint32_t i0 = b0 + tid < n2 ? n2 - 1 - (b0 + tid) : kNone;
-        const uint32_t k = i0 != kNone ? lda(T2.best + i0) : kNone;
+        const SLOT kk = i0 != kNone ? T2.best[i0] : kFree;
         uint32_t tot;
-        const uint32_t rank = c2 + scan(k != kNone ? 1u : 0u, &tot);
-        if (k != kNone) {
-          const Cand c = M.cand[k];
+        const uint32_t rank = c2 + scan(kk != kFree ? 1u : 0u, &tot);
+        if (kk != kFree) {
+          const uint32_t k = (uint32_t)kk;
+          uint32_t ca, cb, cc;
+          if constexpr (RING) {
+            const uint32_t v = M.cpos[k];
+            ca = v & kPosMask; cb = (v >> kPosBits) & kPosMask; cc = (v >> (2 * kPosBits)) & kPosMask;
+          } else {
+            const Cand c = M.cand[k]; ca = c.a; cb = c.b; cc = c.c;
+          }
+          (void)ca;
           const uint32_t slot = (uint32_t)io.slot_base + created + rank;
           uint32_t* hi = io.hit_idx + 26ull * slot;
           hi[0] = io.lstart[l + 2] + i0;
-          hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[c.b];
-          hi[2] = base0 + (uint32_t)T0.kr[c.c];
+          hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[cb];
+          hi[2] = base0 + (uint32_t)T0.kr[cc];
           const uint32_t pos = n_keep + rank;
           if (pos < M.capT) {
-            const float x1 = T1.hx[c.b], y1 = T1.hy[c.b], x2 = T0.hx[c.c], y2 = T0.hy[c.c];
+            const float x1 = T1.hx[cb], y1 = T1.hy[cb], x2 = T0.hx[cc], y2 = T0.hy[cc];
             const float dz = zl - zt[l + 1];
             A.slot[pos] = slot;
-            A.key0[pos] = ((uint32_t)(l + 2) << 22) | i0;
+            A.key0[pos] = ((uint32_t)(l + 2) << M.KSH) | i0;
             A.xa[pos] = x2;
             A.ya[pos] = y2;
             A.tx[pos] = (x2 - x1) / dz;
@@ -779,20 +874,27 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   __shared__ float s_hx[3 * CAPL], s_hy[3 * CAPL];
   __shared__ uint16_t s_kr[3 * CAPL];
   __shared__ uint8_t s_used[3 * CAPL];
-  __shared__ uint32_t s_best[3 * CAPL];
+  __shared__ uint64_t s_best[3 * CAPL];
   __shared__ uint32_t s_bstart[3 * (kNB + 1)];
-  __shared__ uint32_t t_slot[CAPT], t_key0[CAPT], t_tbest[CAPT], t_tmatch[CAPT];
+  __shared__ uint32_t t_slot[CAPT], t_key0[CAPT], t_tmatch[CAPT];
+  __shared__ uint64_t t_tbest[CAPT];
   __shared__ float t_xa[CAPT], t_ya[CAPT], t_tx[CAPT], t_ty[CAPT];
   __shared__ uint8_t t_la[CAPT], t_n[CAPT], t_skip[CAPT];
-  __shared__ Cand s_cand[CAPC];
-  __shared__ uint32_t s_w0[CAPL], s_w1[CAPL], s_wp[CAPL + 1];
+  // candidates (priorities, positions) share their space with the seed doublet
+  // windows: the windows are dead before the first seed candidate is written,
+  // and extension candidates are dead before the windows are built
+  constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u);
+  __shared__ uint64_t s_cw[((kCandBytes > kWinBytes ? kCandBytes : kWinBytes) + 7u) / 8u];
   __shared__ Dbl s_dbl[CAPD];
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
-  M.w0 = s_w0; M.w1 = s_w1; M.wp = s_wp; M.dbl = s_dbl; M.capD = CAPD;
+  uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
+  M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = s_dbl; M.capD = CAPD;
   M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
-  M.T = TrackTab{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
-  M.cand = s_cand;
+  M.T = TrackTab<uint64_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
+  M.cand = nullptr;
+  M.cprio = s_cw;
+  M.cpos = cw + 2 * CAPC;
   M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
   // work items: events 0..n-1 or list[0..count); round robin over the grid, or
   // stolen from the `steal` counter (persistent workgroups) when it is given
@@ -831,9 +933,11 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.used = g.used + b;
     M.best = g.best + b;
     const uint64_t tb = b / 3;
-    M.T = TrackTab{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
+    M.T = TrackTab<uint32_t>{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
                    g.la + tb, g.n + tb, g.skip + tb, g.tbest + tb, g.tmatch + tb};
     M.cand = g.cand + (size_t)blockIdx.x * VELO_MAX_CANDIDATES;
+    M.cprio = nullptr;
+    M.cpos = nullptr;
     M.capL = ne;
     M.capT = (uint32_t)((b + ne) / 3 - b / 3);
     M.capC = VELO_MAX_CANDIDATES;
