@@ -45,3 +45,15 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+
+
+def source_digest() -> str:
+    """sha256 over the kernel sources and the C ABI header (identifies the
+    kernels a stored hardware-counter measurement belongs to)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sources() + [os.path.join(ROOT, "include", "velo.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()

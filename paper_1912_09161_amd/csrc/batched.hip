@@ -195,7 +195,7 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
     if (e != hipSuccess) return e;
   }
   if (stages & 2) {
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 2u);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 3u);
     const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2};
     hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
                                    c.ws, s, fc);

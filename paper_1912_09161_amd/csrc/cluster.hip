@@ -25,6 +25,7 @@ constexpr uint32_t kSmallCap = 512;   // words per segment handled by one wave
 constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
 static_assert(kMidCap >= (uint32_t)kPix, "the workspace row table lives at the segment's own positions");
 constexpr int kMidThreads = 256;
+static_assert(kSmallCap % 64 == 0 && kMidCap % kMidThreads == 0, "register staging of the words");
 constexpr uint32_t kDupBit = 0x80000000u;
 
 struct HitsOut {
@@ -112,16 +113,34 @@ struct SegScratch {
 // union-find roots are the smallest positions (= addresses), so the roots in
 // position order are the clusters in key order and their ranks are a prefix
 // count.
-template <int NT, bool PACKED>
+//
+// MAXW > 0: n <= MAXW * NT, the words are loaded once into registers (all
+// loads in flight together); MAXW == 0: any n, the words are read twice.
+template <int NT, bool PACKED, uint32_t MAXW>
 __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, uint32_t layer,
                                     const SegScratch<PACKED>& S, HitsOut o, uint64_t out_base) {
   constexpr uint32_t WPL = (RowTab<PACKED>::kWords + NT - 1) / NT;  // row words per lane
   const uint32_t tid = threadIdx.x;
   const RowTab<PACKED> rt{S.rows};
+  constexpr uint32_t RW = MAXW > 0 ? MAXW : 1;
+  uint32_t wr[RW];
+  if constexpr (MAXW > 0) {
+#pragma unroll
+    for (uint32_t k = 0; k < MAXW; ++k) {
+      const uint32_t i = tid + k * NT;
+      wr[k] = i < n ? w[i] : 0u;
+    }
+  }
   for (uint32_t i = tid; i < RowTab<PACKED>::kWords; i += NT) S.rows[i] = 0;
   if (tid == 0) *S.flag = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += NT) rt.add(w_row(w[i]));
+  if constexpr (MAXW > 0) {
+#pragma unroll
+    for (uint32_t k = 0; k < MAXW; ++k)
+      if (tid + k * NT < n) rt.add(w_row(wr[k]));
+  } else {
+    for (uint32_t i = tid; i < n; i += NT) rt.add(w_row(w[i]));
+  }
   __syncthreads();
   {  // row starts: exclusive prefix over rows, WPL consecutive words per lane
     const uint32_t w0 = tid * WPL;
@@ -148,9 +167,15 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
   }
   __syncthreads();
   // row buckets (staged in par); afterwards the table holds the row ends
-  for (uint32_t i = tid; i < n; i += NT) {
-    const uint32_t v = w[i];
+  auto stage = [&](uint32_t v) {
     S.par[rt.add(w_row(v))] = ((w_row(v) << 11 | w_col(v)) << 4) | w_charge(v);
+  };
+  if constexpr (MAXW > 0) {
+#pragma unroll
+    for (uint32_t k = 0; k < MAXW; ++k)
+      if (tid + k * NT < n) stage(wr[k]);
+  } else {
+    for (uint32_t i = tid; i < n; i += NT) stage(w[i]);
   }
   __syncthreads();
   // address order: row start + smaller columns in the row; equal columns are
@@ -340,7 +365,7 @@ __device__ __forceinline__ void small_segment(const SmallArgs& a, SmallLds& S, u
   }
   uint32_t cnt = 0;
   if (n > 0)
-    cnt = cluster_segment<64, true>(a.px + b + s0, n, l, S.scratch(), a.o, b + s0);
+    cnt = cluster_segment<64, true, kSmallCap / 64>(a.px + b + s0, n, l, S.scratch(), a.o, b + s0);
   if (threadIdx.x == 0) a.layer_nhits[seg] = cnt;
 }
 
@@ -394,7 +419,7 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
     uint32_t cnt;
     if (n <= kMidCap) {
       const SegScratch<true> S{rows, srt, par, qs, nullptr, scr, tmp, &flag};
-      cnt = cluster_segment<kMidThreads, true>(px + b + s0, n, l, S, o, b + s0);
+      cnt = cluster_segment<kMidThreads, true, kMidCap / kMidThreads>(px + b + s0, n, l, S, o, b + s0);
     } else {
       // scratch in the workspace at the segment's own word positions (n > kPix,
       // so the row table fits there too)
@@ -402,7 +427,7 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
       const SegScratch<false> S{ws + p0, ws + n_pixels + p0, ws + 2 * n_pixels + p0,
                                 ws + 3 * n_pixels + p0, ws + 4 * n_pixels + p0,
                                 ws64 + p0, tmp, &flag};
-      cnt = cluster_segment<kMidThreads, false>(px + p0, n, l, S, o, p0);
+      cnt = cluster_segment<kMidThreads, false, 0>(px + p0, n, l, S, o, p0);
     }
     if (threadIdx.x == 0) layer_nhits[seg] = cnt;
     __syncthreads();

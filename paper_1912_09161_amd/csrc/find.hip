@@ -24,11 +24,11 @@
 // slots, hit lists and counts are written directly; no atomics decide an
 // output position.
 //
-// Three tiers share one implementation: one wave with small LDS tables, 256
-// lanes with large LDS tables, and 256 lanes reading the bucket tables in
-// place with per-event scratch in the caller's workspace at the event's own
-// hit / track positions.  An event whose tables outgrow its tier is re-run
-// from scratch by the next tier.
+// Four tiers share one implementation: 256 lanes with small, middle and large
+// LDS tables, and 256 lanes reading the bucket tables in place with per-event
+// scratch in the caller's workspace at the event's own hit / track positions.
+// An event whose tables outgrow its tier is re-run from scratch by the next
+// tier.
 #include "velo_device.hpp"
 
 namespace velo {
@@ -89,10 +89,9 @@ template <bool RING> struct CandSlot { using T = uint32_t; static constexpr uint
 template <> struct CandSlot<true> { using T = uint64_t; static constexpr uint64_t kFree = ~0ull; };
 constexpr uint32_t kPosBits = 10, kPosMask = (1u << kPosBits) - 1u, kAccepted = 1u << 31;
 
-struct Dbl {
-  uint32_t i01;  // h0 | h1 << 16 (bucket positions)
-  float tx, ty;
-};
+// seed doublet: h0 | h1 << 16 (bucket positions); its slopes are recomputed
+// from the hits, by the same expressions, when the third hit is searched
+using Dbl = uint32_t;
 
 struct EventIO {
   const float* X;          // coordinates of the event's hits in bucket order
@@ -580,7 +579,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
                 float tx, ty;
                 if (!doublet(x0[q], y0[q], x1, y1, tx, ty)) continue;
                 const uint32_t d = atomicAdd(&sc.nd, 1u);
-                if (d < M.capD) M.dbl[d] = Dbl{pj[q] | (i1 << 16), tx, ty};
+                if (d < M.capD) M.dbl[d] = pj[q] | (i1 << 16);
               }
             }
             j = stop;
@@ -592,7 +591,10 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         // (c) third hits, one doublet per lane
         for (uint32_t d = tid; d < nd; d += NT) {
           const Dbl r = M.dbl[d];
-          triplets(r.i01 & 0xFFFFu, r.i01 >> 16, r.tx, r.ty);
+          const uint32_t i0 = r & 0xFFFFu, i1 = r >> 16;
+          const float tx = (T1.hx[i1] - T2.hx[i0]) / dz01;
+          const float ty = (T1.hy[i1] - T2.hy[i0]) / dz01;
+          triplets(i0, i1, tx, ty);
         }
       } else {
         for (uint32_t i1 = tid; i1 < n1; i1 += NT) {
@@ -909,7 +911,7 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
 
 // Workspace tier: any event size.
 constexpr int kGThreads = 256;
-constexpr uint32_t kGBlocks = 64;
+constexpr uint32_t kGBlocks = 128;
 
 struct GlobalTabs {
   uint32_t* best; uint8_t* used;                                      // [n_pixels]
@@ -956,14 +958,18 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
 constexpr uint32_t kSCapL = 256, kSCapT = 256, kSCapC = 384, kSCapD = 512;
-// large LDS tier: persistent workgroups over the events the small tier hands on
+// middle and large LDS tiers: persistent workgroups over the events the tier
+// below hands on
+constexpr int kMThreads = 256;
+constexpr uint32_t kMCapL = 512, kMCapT = 512, kMCapC = 1024, kMCapD = 2048, kMBlocks = 512;
+static_assert(kMCapL <= (1u << kPosBits) && kMCapT <= (1u << kPosBits), "packed positions");
 constexpr int kLThreads = 256;
-constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 2048, kLBlocks = 256;
+constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, kLBlocks = 256;
 
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct FindWs {
-  uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *order, *bst;
+  uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *esc3_count, *esc3_list, *order, *bst;
   float *xs, *ys;
   GlobalTabs g;
 };
@@ -978,6 +984,8 @@ static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, Find
   f.esc_list = (uint32_t*)take(4ull * n_events);
   f.esc2_count = (uint32_t*)take(4);
   f.esc2_list = (uint32_t*)take(4ull * n_events);
+  f.esc3_count = (uint32_t*)take(4);
+  f.esc3_list = (uint32_t*)take(4ull * n_events);
   f.order = (uint32_t*)take(4ull * n_pixels);
   f.xs = (float*)take(4ull * n_pixels);
   f.ys = (float*)take(4ull * n_pixels);
@@ -1023,7 +1031,7 @@ struct FindCfg {
   int small_threads;          // 128 or 256 lanes per event in the small tier
   uint32_t small_grid;        // 0: one workgroup per event; else persistent work stealing
   const uint32_t* ev_order;   // descending-size order of the events (work stealing)
-  uint32_t* counters;         // [2] zeroed work-stealing counters (work stealing)
+  uint32_t* counters;         // [3] zeroed work-stealing counters (work stealing)
 };
 
 hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
@@ -1036,6 +1044,7 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   const FindConst c = make_find_const(p);
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc_count, 0u, f.esc_count);
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc3_count, 0u, f.esc3_count);
   hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
                      h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.xs, f.ys, f.bst);
   const bool ws_mode = cfg.small_grid != 0;
@@ -1051,11 +1060,17 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   FindArgs a2 = a;
   a2.esc_count = f.esc2_count;
   a2.esc_list = f.esc2_list;
-  hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(kLBlocks),
-                     dim3(kLThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count,
+  hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), dim3(kMBlocks),
+                     dim3(kMThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count,
                      ws_mode ? cfg.counters + 1 : (uint32_t*)nullptr);
-  hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a2, c, f.g, f.esc2_list,
-                     f.esc2_count);
+  FindArgs a3 = a;
+  a3.esc_count = f.esc3_count;
+  a3.esc_list = f.esc3_list;
+  hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(kLBlocks),
+                     dim3(kLThreads), 0, s, a3, c, n_events, f.esc2_list, f.esc2_count,
+                     ws_mode ? cfg.counters + 2 : (uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a3, c, f.g, f.esc3_list,
+                     f.esc3_count);
   return hipGetLastError();
 }
 

@@ -113,7 +113,10 @@ def choose_threshold(logit: np.ndarray, particle: np.ndarray, reconstructible: n
     particle the track is matched to, or -1; reconstructible: unique ids of
     the reconstructible particles.  A particle counts as found when one of its
     matched tracks is accepted, so it is found at threshold c iff its best
-    matched logit is >= c."""
+    matched logit is >= c.  The result is always a finite binary32 value: if
+    no threshold reaches target_eff, the one of the highest reachable
+    efficiency; if any does (target <= 0), the largest finite value."""
+    f32 = np.finfo(np.float32)
     reco = np.unique(reconstructible)
     n_reco = len(reco)
     m = particle >= 0
@@ -124,7 +127,7 @@ def choose_threshold(logit: np.ndarray, particle: np.ndarray, reconstructible: n
     vals = np.sort(np.array([best[p] for p in reco.tolist() if p in best], np.float64))[::-1]
     need = int(np.ceil(target_eff * n_reco - 1e-9))
     if need <= 0:
-        return float("inf")
-    if need > len(vals):
-        return float("-inf")
-    return float(np.float32(vals[need - 1]))
+        return float(f32.max)
+    if len(vals) == 0:
+        return float(f32.min)
+    return float(np.float32(vals[min(need, len(vals)) - 1]))
