@@ -960,10 +960,10 @@ constexpr int kSThreads = 256;
 constexpr uint32_t kSCapL = 256, kSCapT = 256, kSCapC = 384, kSCapD = 512;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
-constexpr int kMThreads = 256;
+constexpr int kMThreads = 512;
 constexpr uint32_t kMCapL = 512, kMCapT = 512, kMCapC = 1024, kMCapD = 2048, kMBlocks = 512;
 static_assert(kMCapL <= (1u << kPosBits) && kMCapT <= (1u << kPosBits), "packed positions");
-constexpr int kLThreads = 256;
+constexpr int kLThreads = 512;
 constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, kLBlocks = 256;
 
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
