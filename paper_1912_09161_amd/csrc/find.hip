@@ -216,7 +216,7 @@ struct FindScal {
   uint32_t n_act;    // active tracks
   uint32_t n_created;
   uint32_t fail;     // 0 ok, 1 escalate, 2 overflow
-  uint32_t tmp[2][8];  // scan scratch, two alternating buffers of NT/64 words
+  uint32_t tmp[2][16];  // scan scratch, two alternating buffers of NT/64 words
   uint32_t lstart[27], lnh[26];  // plane tables of the event
   float z[kLayers];              // plane positions
 };
@@ -963,7 +963,7 @@ constexpr uint32_t kSCapL = 256, kSCapT = 256, kSCapC = 384, kSCapD = 512;
 constexpr int kMThreads = 512;
 constexpr uint32_t kMCapL = 512, kMCapT = 512, kMCapC = 1024, kMCapD = 2048, kMBlocks = 512;
 static_assert(kMCapL <= (1u << kPosBits) && kMCapT <= (1u << kPosBits), "packed positions");
-constexpr int kLThreads = 512;
+constexpr int kLThreads = 1024;
 constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, kLBlocks = 256;
 
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
