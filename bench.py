@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--events", type=int, default=1000, help="events per batch (one step)")
     ap.add_argument("--batches", type=int, default=8, help="distinct device-resident batches")
-    ap.add_argument("--streams", type=int, default=4, help="concurrent HIP streams")
+    ap.add_argument("--streams", type=int, default=6, help="concurrent HIP streams")
     ap.add_argument("--cpu-events", type=int, default=0,
                     help="oracle sample size (default: all generated nominal events)")
     ap.add_argument("--no-cpu", action="store_true")

@@ -65,33 +65,48 @@ __device__ __forceinline__ uint32_t ev_class(const uint64_t* offsets, uint64_t n
 }
 
 constexpr int kOrderThreads = 256;
-constexpr uint32_t kOrderItems = 8;  // segments per lane of the ordering kernels
+constexpr uint32_t kOrderSegs = 1u, kOrderEvents = 2u;  // which orders to build
 
-// Per-workgroup LDS histograms of the segment and event size classes of the
-// workgroup's range of segments (kOrderItems * kOrderThreads of them).
-__device__ __forceinline__ void order_block_hist(const uint64_t* offsets, const uint32_t* status,
-                                                 const uint32_t* layer_start, uint32_t n_events,
-                                                 uint64_t n_pixels, uint32_t* sh, uint32_t* eh) {
-  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads) sh[k] = 0;
-  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads) eh[k] = 0;
-  __syncthreads();
-  const uint32_t nseg = n_events * kLayers;
-  const uint32_t s0 = blockIdx.x * kOrderThreads * kOrderItems;
-  for (uint32_t j = 0; j < kOrderItems; ++j) {
-    const uint32_t seg = s0 + j * kOrderThreads + threadIdx.x;
-    if (seg >= nseg) break;
-    atomicAdd(sh + seg_class(offsets, status, layer_start, n_pixels, seg), 1u);
-    if (seg % kLayers == 0) atomicAdd(eh + ev_class(offsets, n_pixels, seg / kLayers), 1u);
+// Items of the ordering kernels, one per lane: the (event, plane) segments
+// when their order is wanted (the first segment of every event also counts
+// the event), else the events.
+__host__ __device__ __forceinline__ uint32_t order_items(uint32_t n_events, uint32_t mode) {
+  return (mode & kOrderSegs) ? n_events * kLayers : n_events;
+}
+
+// Segment and event classes of one item (0xFFFFFFFF when it has none).
+__device__ __forceinline__ void order_classes(const uint64_t* offsets, const uint32_t* status,
+                                              const uint32_t* layer_start, uint32_t n_events,
+                                              uint64_t n_pixels, uint32_t mode, uint32_t item,
+                                              uint32_t* sc, uint32_t* ec, uint32_t* ev) {
+  *sc = 0xFFFFFFFFu;
+  *ec = 0xFFFFFFFFu;
+  *ev = 0xFFFFFFFFu;
+  if (item >= order_items(n_events, mode)) return;
+  if (mode & kOrderSegs) {
+    *sc = seg_class(offsets, status, layer_start, n_pixels, item);
+    if ((mode & kOrderEvents) && item % kLayers == 0) *ev = item / kLayers;
+  } else {
+    *ev = item;
   }
-  __syncthreads();
+  if (*ev != 0xFFFFFFFFu) *ec = ev_class(offsets, n_pixels, *ev);
 }
 
 // class sizes: LDS histograms per workgroup, one global add per non-empty bin
 __global__ __launch_bounds__(kOrderThreads) void k_order_hist(
     const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
-    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, OrderWs w) {
+    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, uint32_t mode,
+    OrderWs w) {
   __shared__ uint32_t sh[kSegClasses], eh[kEvClasses];
-  order_block_hist(offsets, status, layer_start, n_events, n_pixels, sh, eh);
+  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads) sh[k] = 0;
+  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads) eh[k] = 0;
+  __syncthreads();
+  uint32_t sc, ec, ev;
+  order_classes(offsets, status, layer_start, n_events, n_pixels, mode,
+                blockIdx.x * kOrderThreads + threadIdx.x, &sc, &ec, &ev);
+  if (sc != 0xFFFFFFFFu) atomicAdd(sh + sc, 1u);
+  if (ec != 0xFFFFFFFFu) atomicAdd(eh + ec, 1u);
+  __syncthreads();
   for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads)
     if (sh[k]) atomicAdd(w.seg_hist + k, sh[k]);
   for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads)
@@ -116,25 +131,26 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_scan(OrderWs w) {
 // take positions in it with LDS atomics (order inside a class is arbitrary)
 __global__ __launch_bounds__(kOrderThreads) void k_order_scatter(
     const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ status,
-    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, OrderWs w) {
+    const uint32_t* __restrict__ layer_start, uint32_t n_events, uint64_t n_pixels, uint32_t mode,
+    OrderWs w) {
   __shared__ uint32_t sh[kSegClasses], eh[kEvClasses];
-  order_block_hist(offsets, status, layer_start, n_events, n_pixels, sh, eh);
+  for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads) sh[k] = 0;
+  for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads) eh[k] = 0;
+  __syncthreads();
+  uint32_t sc, ec, ev;
+  const uint32_t item = blockIdx.x * kOrderThreads + threadIdx.x;
+  order_classes(offsets, status, layer_start, n_events, n_pixels, mode, item, &sc, &ec, &ev);
+  uint32_t ps = 0, pe = 0;  // rank inside the workgroup's share of the class
+  if (sc != 0xFFFFFFFFu) ps = atomicAdd(sh + sc, 1u);
+  if (ec != 0xFFFFFFFFu) pe = atomicAdd(eh + ec, 1u);
+  __syncthreads();
   for (uint32_t k = threadIdx.x; k < kSegClasses; k += kOrderThreads)
     if (sh[k]) sh[k] = atomicAdd(w.seg_hist + k, sh[k]);
   for (uint32_t k = threadIdx.x; k < kEvClasses; k += kOrderThreads)
     if (eh[k]) eh[k] = atomicAdd(w.ev_hist + k, eh[k]);
   __syncthreads();
-  const uint32_t nseg = n_events * kLayers;
-  const uint32_t s0 = blockIdx.x * kOrderThreads * kOrderItems;
-  for (uint32_t j = 0; j < kOrderItems; ++j) {
-    const uint32_t seg = s0 + j * kOrderThreads + threadIdx.x;
-    if (seg >= nseg) break;
-    w.seg_order[atomicAdd(sh + seg_class(offsets, status, layer_start, n_pixels, seg), 1u)] = seg;
-    if (seg % kLayers == 0) {
-      const uint32_t e = seg / kLayers;
-      w.ev_order[atomicAdd(eh + ev_class(offsets, n_pixels, e), 1u)] = e;
-    }
-  }
+  if (sc != 0xFFFFFFFFu) w.seg_order[sh[sc] + ps] = item;
+  if (ec != 0xFFFFFFFFu) w.ev_order[eh[ec] + pe] = ev;
 }
 
 // ---------------------------------------------------------------------------
@@ -174,7 +190,6 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
   const size_t main_ws = c.ws_bytes - order_ws_layout(nullptr, c.n_events, nullptr);
   OrderWs ow;
   order_ws_layout((char*)c.ws + main_ws, c.n_events, &ow);
-  const uint32_t nseg = c.n_events * kLayers;
   if (stages & 1) {
     // clearing, validation, size ordering, clustering
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
@@ -182,13 +197,15 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
                        c.n_events, (uint32_t*)c.ws);
     hipLaunchKernelGGL(k_validate, dim3(c.n_events), dim3(kValThreads), 0, s, c.px, c.offsets,
                        c.n_pixels, c.hits.status, c.hits.layer_start);
-    const uint32_t og = (nseg + kOrderThreads * kOrderItems - 1) / (kOrderThreads * kOrderItems);
-    if (og > 0) {
+    // size orders for the persistent kernels that use them
+    const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
+    if (mode) {
+      const uint32_t og = (order_items(c.n_events, mode) + kOrderThreads - 1) / kOrderThreads;
       hipLaunchKernelGGL(k_order_hist, dim3(og), dim3(kOrderThreads), 0, s, c.offsets, c.hits.status,
-                         c.hits.layer_start, c.n_events, c.n_pixels, ow);
+                         c.hits.layer_start, c.n_events, c.n_pixels, mode, ow);
       hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderThreads), 0, s, ow);
       hipLaunchKernelGGL(k_order_scatter, dim3(og), dim3(kOrderThreads), 0, s, c.offsets,
-                         c.hits.status, c.hits.layer_start, c.n_events, c.n_pixels, ow);
+                         c.hits.status, c.hits.layer_start, c.n_events, c.n_pixels, mode, ow);
     }
     const ClusterCfg cc{k.small_grid, k.mid_grid, ow.seg_order, ow.counters};
     hipError_t e = launch_cluster_cfg(c.px, c.offsets, c.n_events, c.n_pixels, &c.hits, c.ws, s, cc, true);

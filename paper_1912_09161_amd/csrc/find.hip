@@ -29,7 +29,7 @@
 // scratch in the caller's workspace at the event's own hit / track positions.
 // An event whose tables outgrow its tier is re-run from scratch by the next
 // tier.
-#include "velo_device.hpp"
+#include "azimuth.hpp"
 
 namespace velo {
 
@@ -42,7 +42,6 @@ struct FindConst {
   float rho_seed, rho_fwd;  // upper bounds of sqrt(s_seed), sqrt(s_fwd)
 };
 
-constexpr uint32_t kNB = 256;  // azimuth buckets per plane
 
 // One plane, indexed by bucket position p.  The hit's local index (rank of
 // its key in the plane, the order of its event-relative slot) is kr[p].
@@ -143,23 +142,6 @@ struct FindMem {
     }
   }
 };
-
-// Monotone pseudo-angle of (x, y) in [0, 4]; its derivative with respect to
-// the azimuth is between 1/2 and 1, so an azimuth window of half width d is
-// contained in the pseudo-angle window of the same half width.
-__device__ __forceinline__ float pangle(float x, float y) {
-  float ax = fabsf(x), ay = fabsf(y), d = ax + ay;
-  // hardware reciprocal (about 1 ulp): bucket assignment and window centres use
-  // this same function, and every window carries a margin far above its error
-  float r = d > 0.0f ? ay * __builtin_amdgcn_rcpf(d) : 0.0f;
-  if (y >= 0.0f) return x >= 0.0f ? r : 2.0f - r;
-  return x < 0.0f ? 2.0f + r : 4.0f - r;
-}
-
-__device__ __forceinline__ uint32_t bucket_of(float pa, uint32_t nb) {
-  int b = (int)(pa * (float)nb * 0.25f);
-  return b < 0 ? 0u : (b >= (int)nb ? nb - 1 : (uint32_t)b);
-}
 
 // Bucket ranges covering the pseudo-angle window [c - d, c + d] (wrapping).
 struct Ranges { uint32_t b0, b1, b2, b3; };  // [b0,b1] and [b2,b3], b2 > b3 if unused
@@ -355,7 +337,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     pf.commit(io, l, M);
     if (l > 0) pf.issue(io, l - 1, M.capL);
     const auto T0 = M.layer(io, l);
-    const uint32_t n0 = io.lnh[l], base0 = io.lstart[l];
+    const uint32_t base0 = io.lstart[l];
     const float zl = zt[l];
     const uint32_t n_act = sc.n_act;
 
@@ -779,39 +761,12 @@ __global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, 
                                                    const uint32_t* __restrict__ lstart,
                                                    const uint32_t* __restrict__ lnh,
                                                    const uint64_t* __restrict__ offsets,
-                                                   uint64_t n_pixels, uint32_t* __restrict__ order,
-                                                   float* __restrict__ xs, float* __restrict__ ys,
-                                                   uint32_t* __restrict__ bst) {
-  __shared__ uint32_t cnt[kNB], cur[kNB];
+                                                   uint64_t n_pixels, AzOut az) {
+  __shared__ uint32_t cnt[kNB];
   const uint32_t seg = blockIdx.x, e = seg / kLayers, l = seg % kLayers;
   const uint64_t b0 = offsets[e], b1 = offsets[e + 1];
   if (hstatus[e] != 0 || b1 < b0 || b1 > n_pixels) return;
-  const uint32_t n = lnh[seg];
-  const uint64_t base = b0 + lstart[27ull * e + l];
-  uint32_t* bs = bst + (uint64_t)seg * (kNB + 1);
-  for (uint32_t b = threadIdx.x; b < kNB; b += 64) cnt[b] = 0;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += 64)
-    atomicAdd(cnt + bucket_of(pangle(X[base + i], Y[base + i]), kNB), 1u);
-  __syncthreads();
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < kNB; b0 += 64) {
-    const uint32_t b = b0 + threadIdx.x;
-    const uint32_t c = b < kNB ? cnt[b] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_scan<64>(c, nullptr, &tot);
-    if (b < kNB) { bs[b] = carry + ex; cur[b] = carry + ex; }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) bs[kNB] = carry;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += 64) {
-    const float x = X[base + i], y = Y[base + i];
-    const uint64_t p = base + atomicAdd(cur + bucket_of(pangle(x, y), kNB), 1u);
-    order[p] = i;
-    xs[p] = x;
-    ys[p] = y;
-  }
+  azimuth_tables<64>(X, Y, b0 + lstart[27ull * e + l], lnh[seg], seg, cnt, nullptr, az);
 }
 
 struct FindArgs {
@@ -1046,7 +1001,7 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc3_count, 0u, f.esc3_count);
   hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
-                     h->layer_start, h->layer_nhits, offsets, n_pixels, f.order, f.xs, f.ys, f.bst);
+                     h->layer_start, h->layer_nhits, offsets, n_pixels, AzOut{f.order, f.xs, f.ys, f.bst});
   const bool ws_mode = cfg.small_grid != 0;
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
   const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
