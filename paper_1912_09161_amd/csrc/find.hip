@@ -129,6 +129,10 @@ struct FindMem {
   uint32_t* w0;
   uint32_t* w1;
   uint32_t* wp;   // [capL + 1]
+  // forward search (LDS tiers): the same for every active track on the next plane
+  uint32_t* tw0;
+  uint32_t* tw1;
+  uint32_t* twp;  // [capT + 1]
   Dbl* dbl;       // [capD]
   uint32_t capL, capT, capC, capD;
   __device__ __forceinline__ LayerTab<IDX, SLOT> layer(const EventIO& io, int l) const {
@@ -344,32 +348,106 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     // ---- 1. extend active tracks into plane l ----
     // (the seed counters were last read a step ago, several barriers back)
     if (tid == 0) { sc.ncs = 0; sc.nd = 0; }
-    for (uint32_t t = tid; t < n_act; t += NT) {
-      A.tmatch[t] = kNone;
-      A.tbest[t] = kFree;
-      const uint32_t key0 = A.key0[t];
-      const float xa = A.xa[t], ya = A.ya[t], txf = A.tx[t], tyf = A.ty[t];
-      const float za = zt[A.la[t]];
-      const float d = zl - za;
-      const float xp = xa + txf * d;
-      const float yp = ya + tyf * d;
-      Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
-      scan_window(T0, r, [&](uint32_t h, float xh, float yh) {
-        float dx = xh - xp, dy = yh - yp;
-        float s = dx * dx + dy * dy;
-        if (s <= P.s_fwd) {
-          uint32_t k = atomicAdd(&sc.ncf, 1u);
-          if (k < M.capC) {
-            if constexpr (RING) {
-              M.cprio[k] = ((uint64_t)__float_as_uint(s) << 32) | ((uint64_t)key0 << kPosBits) |
-                           (uint64_t)T0.kr[h];
-              M.cpos[k] = t | (h << kPosBits);
-            } else {
-              M.cand[k] = Cand{s, t, h, 0u};
+    // extrapolation of track t to plane l
+    auto extrap = [&](uint32_t t, float& xp, float& yp) {
+      const float d = zl - zt[A.la[t]];
+      xp = A.xa[t] + A.tx[t] * d;
+      yp = A.ya[t] + A.ty[t] * d;
+    };
+    auto add_ext = [&](uint32_t t, uint32_t key0, uint32_t h, float s) {
+      uint32_t k = atomicAdd(&sc.ncf, 1u);
+      if (k < M.capC) {
+        if constexpr (RING) {
+          M.cprio[k] = ((uint64_t)__float_as_uint(s) << 32) | ((uint64_t)key0 << kPosBits) |
+                       (uint64_t)T0.kr[h];
+          M.cpos[k] = t | (h << kPosBits);
+        } else {
+          M.cand[k] = Cand{s, t, h, 0u};
+        }
+      }
+    };
+    // Big events (the middle and large tiers) have long windows of uneven length:
+    // there the (track, hit) pairs are balanced over the lanes; small events
+    // scan each track's window in its own lane.
+    if constexpr (RING && NT >= 512) {
+      // (a) window of every active track, prefix of the window sizes
+      uint32_t carry = 0;
+      for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
+        const uint32_t t = b0 + tid;
+        uint32_t cnt = 0;
+        if (t < n_act) {
+          A.tmatch[t] = kNone;
+          A.tbest[t] = kFree;
+          float xp, yp;
+          extrap(t, xp, yp);
+          const Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
+          const uint32_t s0 = T0.bstart[r.b0], l0 = T0.bstart[r.b1 + 1] - s0;
+          uint32_t s1 = 0, l1 = 0;
+          if (r.b2 <= r.b3) { s1 = T0.bstart[r.b2]; l1 = T0.bstart[r.b3 + 1] - s1; }
+          M.tw0[t] = s0 | (l0 << 16);
+          M.tw1[t] = s1 | (l1 << 16);
+          cnt = l0 + l1;
+        }
+        uint32_t tot;
+        const uint32_t ex = scan(cnt, &tot);
+        if (t < n_act) M.twp[t] = carry + ex;
+        carry += tot;
+      }
+      if (tid == 0) M.twp[n_act] = carry;
+      wg_barrier<RING>();
+      // (b) all (track, hit) pairs, split evenly over the lanes in contiguous
+      // chunks; four pairs of one track per step, their loads issued together
+      const uint32_t total = carry, per = (total + NT - 1) / NT;
+      uint32_t j = tid * per;
+      const uint32_t jend = j + per < total ? j + per : total;
+      if (j < jend) {
+        uint32_t lo = 0, hi = n_act - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (M.twp[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        for (uint32_t t = lo; j < jend; ++t) {
+          const uint32_t wb = M.twp[t], we = M.twp[t + 1];
+          if (we <= j) continue;
+          const uint32_t w0 = M.tw0[t], w1 = M.tw1[t], l0 = w0 >> 16, key0 = A.key0[t];
+          float xp, yp;
+          extrap(t, xp, yp);
+          const uint32_t stop = we < jend ? we : jend;
+          for (uint32_t g = j; g < stop; g += 4) {
+            uint32_t ph[4];
+            float xh[4], yh[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+              const uint32_t k = (g + q < stop ? g + q : stop - 1) - wb;
+              ph[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
+              xh[q] = T0.hx[ph[q]];
+              yh[q] = T0.hy[ph[q]];
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+              if (g + q >= stop) continue;
+              const float dx = xh[q] - xp, dy = yh[q] - yp;
+              const float s = dx * dx + dy * dy;
+              if (s <= P.s_fwd) add_ext(t, key0, ph[q], s);
             }
           }
+          j = stop;
         }
-      });
+      }
+    } else {
+      for (uint32_t t = tid; t < n_act; t += NT) {
+        A.tmatch[t] = kNone;
+        A.tbest[t] = kFree;
+        const uint32_t key0 = A.key0[t];
+        float xp, yp;
+        extrap(t, xp, yp);
+        Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
+        scan_window(T0, r, [&](uint32_t h, float xh, float yh) {
+          const float dx = xh - xp, dy = yh - yp;
+          const float s = dx * dx + dy * dy;
+          if (s <= P.s_fwd) add_ext(t, key0, h, s);
+        });
+      }
     }
     wg_barrier<RING>();
     {
@@ -843,8 +921,10 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u);
   __shared__ uint64_t s_cw[((kCandBytes > kWinBytes ? kCandBytes : kWinBytes) + 7u) / 8u];
   __shared__ Dbl s_dbl[CAPD];
+  __shared__ uint32_t s_tw[3 * CAPT + 1];
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
+  M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
   M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = s_dbl; M.capD = CAPD;
   M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
@@ -899,6 +979,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.capT = (uint32_t)((b + ne) / 3 - b / 3);
     M.capC = VELO_MAX_CANDIDATES;
     M.w0 = M.w1 = M.wp = nullptr;
+    M.tw0 = M.tw1 = M.twp = nullptr;
     M.dbl = nullptr;
     M.capD = 0;
     if (run_event<kGThreads>(a, P, M, sc, e) && threadIdx.x == 0) {
