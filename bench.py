@@ -22,7 +22,8 @@ distinct batches with their own outputs, so the 256 MB Infinity Cache cannot
 hold the working set.
 
 A second leg repeats both forms on high-occupancy events (the stress
-sample).  Prints one JSON line: events/s of every form, the HBM roofline of
+sample); a third times 100k events of uneven occupancy in one launch per
+stage (plain) or one graph replay (batched), the batched form's use case.  Prints one JSON line: events/s of every form, the HBM roofline of
 the dominant stage (stage durations from HIP events recorded on the launch
 streams), physics figures of merit from generator truth, and the CPU oracle's
 throughput on a bounded sample of the nominal events.
@@ -46,6 +47,8 @@ WORKLOAD = ("nominal occupancy: 1000 events/batch, 26 planes, PVs/event Poisson(
             "50 urad scattering; uint32 raw words, binary32 hits and fits")
 STRESS = ("high occupancy: 1000 events/batch, PVs/event Poisson(20), noise 1e-4/px, 95% hit "
           "efficiency, 100 urad scattering, X/X0 2.38e-3 per plane")
+UNEVEN = ("uneven occupancy in one launch: PVs/event uniform 1..15 (about 25-375 tracks per event), "
+          "otherwise nominal")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "velo_hbm_traffic_nominal.json")
 
 
@@ -69,6 +72,8 @@ def parse():
     ap.add_argument("--stress-val", type=int, default=1000)
     ap.add_argument("--stress-batches", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--uneven-events", type=int, default=100_000,
+                    help="events of the uneven-occupancy batch timed in one launch (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the run, 4 device-to-device copies of this many MiB (calibrates HBM "
                          "byte counters against a transfer of known size)")
@@ -292,6 +297,7 @@ def main():
     if not args.no_learned:
         mlp, info = train(velo, torch, "learn_train", args.train_events, "learn_val", args.val_events, 0,
                           params, args.epochs, dev)
+        mlp_nominal = mlp
         wall, cfg = time_batched(velo, torch, bufs, streams, params, mlp, args.steps, args.warmup)
         value = args.steps * n_ev / wall
         forms["batched_mlp"] = dict(value=round(value, 1), ms_per_step=round(wall * 1e3 / args.steps, 5),
@@ -329,6 +335,28 @@ def main():
         del sbufs, swss
         torch.cuda.empty_cache()
 
+    # ---- uneven occupancy, the whole batch in one launch per stage / one graph
+    uneven = None
+    if args.uneven_events > 0:
+        t2 = time.time()
+        ub = generate("uneven", args.uneven_events, workers=WORKERS)
+        ugen = time.time() - t2
+        ubuf = to_device(velo, torch, [ub], dev)
+        uws = [velo.alloc_workspace(ubuf[0]["N"], ubuf[0]["E"], dev)]
+        ust = streams[:1]
+        usteps = max(3, args.steps // 100)
+        uw, _ = time_plain(velo, torch, ubuf, ust, uws, params, usteps, 1)
+        uneven = dict(workload=UNEVEN, events=ub.n_events, pixels_per_event=round(ub.n_pixels / ub.n_events, 1),
+                      steps=usteps, gen_seconds=round(ugen, 1),
+                      plain=dict(value=round(usteps * ub.n_events / uw, 1)))
+        del uws
+        torch.cuda.empty_cache()
+        if not args.no_learned:
+            wall, cfg = time_batched(velo, torch, ubuf, ust, params, mlp_nominal, usteps, 1)
+            uneven["batched_mlp"] = dict(value=round(usteps * ub.n_events / wall, 1), autotuned=cfg)
+        del ubuf
+        torch.cuda.empty_cache()
+
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -358,7 +386,7 @@ def main():
         config=dict(workload=WORKLOAD, events_per_step=n_ev, rotating_batches=R, streams=S,
                     form="plain" if args.no_learned else "batched_mlp",
                     pixels_per_event=round(per["px"] / E, 1)),
-        roofline=roofline, stages=stages, forms=forms, stress=stress, cpu_baseline=cpu,
+        roofline=roofline, stages=stages, forms=forms, stress=stress, uneven=uneven, cpu_baseline=cpu,
         gen_seconds=round(gen_s, 1),
     )
     print(json.dumps(out))
