@@ -921,7 +921,7 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u);
   __shared__ uint64_t s_cw[((kCandBytes > kWinBytes ? kCandBytes : kWinBytes) + 7u) / 8u];
   __shared__ Dbl s_dbl[CAPD];
-  __shared__ uint32_t s_tw[3 * CAPT + 1];
+  __shared__ uint32_t s_tw[NT >= 512 ? 3 * CAPT + 1 : 1];  // balanced forward search only
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
   M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
-constexpr uint32_t kSCapL = 256, kSCapT = 256, kSCapC = 384, kSCapD = 512;
+constexpr uint32_t kSCapL = 320, kSCapT = 256, kSCapC = 384, kSCapD = 512;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;
