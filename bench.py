@@ -105,12 +105,27 @@ def labels(B, b):
 
 
 def figures(uid, accepted, reco):
+    """Efficiency, ghost and clone rates with binomial standard errors."""
     from synth.truth import efficiency_ghosts
     m = efficiency_ghosts(uid, accepted, reco)
+    n_reco = max(len(np.unique(reco)), 1)
+    m["efficiency_err"] = float(np.sqrt(m["efficiency"] * (1 - m["efficiency"]) / n_reco))
+    m["ghost_rate_err"] = float(np.sqrt(m["ghost_rate"] * (1 - m["ghost_rate"]) / max(m["n_tracks"], 1)))
     return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in m.items()}
 
 
-def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_events=False):
+def repeats(run, steps, n_ev, n=10):
+    """The paper's protocol: n measurements over different event sets (the
+    batches rotate), mean and standard deviation of events/s."""
+    per = max(1, steps // n)
+    rates = []
+    for r in range(n):
+        rates.append(per * n_ev / run(per, r * per))
+    return dict(n=n, steps_each=per, mean=round(float(np.mean(rates)), 1),
+                std=round(float(np.std(rates, ddof=1)), 1))
+
+
+def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_events=False, first=0):
     R, S = len(bufs), len(streams)
 
     def step(i, ev=None):
@@ -134,7 +149,7 @@ def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_even
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)] if with_events else None
     w0 = time.perf_counter()
     for i in range(steps):
-        step(i, events[i] if with_events else None)
+        step(first + i, events[i] if with_events else None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     if not with_events:
@@ -147,7 +162,7 @@ def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_even
     return max(wall, span), stage_ms / steps
 
 
-def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup):
+def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup, n_repeats=0):
     R, S = len(bufs), len(streams)
     dev = bufs[0]["px"].device
     ctxs = [velo.Context() for _ in range(S)]
@@ -161,20 +176,26 @@ def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup):
                             bufs=dict(hits=B["hits"], tracks=B["tracks"], states=B["states"], ws=wss[k]),
                             stream=streams[k])
 
-    for i in range(max(warmup, 2 * R)):  # autotune, then capture every (batch, stream) graph
+    import math
+    for i in range(max(warmup, R * S // math.gcd(R, S))):  # autotune, then capture every (batch, stream) graph
         step(i)
     torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for i in range(steps):
-        step(i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
+    def run(n, first):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(n):
+            step(first + i)
+        torch.cuda.synchronize()
+        return time.perf_counter() - w0
+
+    wall = run(steps, 0)
+    rep = repeats(run, steps, bufs[0]["E"], n_repeats) if n_repeats else None
     step(0)  # leave batch 0's outputs from this form
     torch.cuda.synchronize()
     cfg = ctxs[0].config()
     for c in ctxs:
         c.close()
-    return wall, cfg
+    return wall, cfg, rep
 
 
 def train(velo, torch, train_cfg, n_train, val_cfg, n_val, val_first, params, epochs, dev):
@@ -255,6 +276,8 @@ def main():
     elapsed, stage_ms = time_plain(velo, torch, bufs, streams, wss, params, args.steps, args.warmup,
                                    with_events=True)
     plain_value = args.steps * n_ev / elapsed
+    plain_rep = repeats(lambda n, first: time_plain(velo, torch, bufs, streams, wss, params, n, 0, first=first)[0],
+                        args.steps, n_ev)
 
     # algorithmic bytes per launch of each stage, from the batch contents
     tot = dict(px=0, hits=0, tracks=0, trk_hits=0)
@@ -279,13 +302,19 @@ def main():
     stages = []
     for name, ms, by in (("cluster", stage_ms[0], b_cluster), ("find_tracks", stage_ms[1], b_find),
                          ("fit", stage_ms[2], b_fit)):
-        stages.append(dict(stage=name, ms=round(ms, 5), bytes=int(by), gbs=round(by / ms / 1e6, 1)))
+        stages.append(dict(stage=name, ms=round(ms, 5), bytes=int(by), gbs=round(by / ms / 1e6, 1),
+                           frac=round(by / ms / 1e6 / HBM_PEAK_GBS, 5)))
+    # whole pipeline: algorithmic bytes of all stages at the measured step rate
+    overall = dict(bytes=int(b_cluster + b_find + b_fit),
+                   gbs=round((b_cluster + b_find + b_fit) * plain_value / n_ev / 1e9, 1))
+    overall["frac"] = round(overall["gbs"] / HBM_PEAK_GBS, 5)
     dom = max(stages, key=lambda s: s["ms"])
     roofline = dict(bound="hbm", achieved=dom["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(dom["gbs"] / HBM_PEAK_GBS, 5), traffic=stored_traffic(dom["stage"]),
                     kernel=dom["stage"], per_event_bytes=round(dom["bytes"] / E, 1))
 
-    forms = dict(plain=dict(value=round(plain_value, 1), ms_per_step=round(elapsed * 1e3 / args.steps, 5)))
+    forms = dict(plain=dict(value=round(plain_value, 1), ms_per_step=round(elapsed * 1e3 / args.steps, 5),
+                            repeats=plain_rep, hbm_overall=overall))
     lab0 = None
     if not args.no_physics:
         lab0 = labels(bufs[0], batches[0])
@@ -298,10 +327,11 @@ def main():
         mlp, info = train(velo, torch, "learn_train", args.train_events, "learn_val", args.val_events, 0,
                           params, args.epochs, dev)
         mlp_nominal = mlp
-        wall, cfg = time_batched(velo, torch, bufs, streams, params, mlp, args.steps, args.warmup)
+        wall, cfg, brep = time_batched(velo, torch, bufs, streams, params, mlp, args.steps, args.warmup,
+                                       n_repeats=10)
         value = args.steps * n_ev / wall
         forms["batched_mlp"] = dict(value=round(value, 1), ms_per_step=round(wall * 1e3 / args.steps, 5),
-                                    training=info, autotuned=cfg)
+                                    repeats=brep, training=info, autotuned=cfg)
         if lab0 is not None:
             forms["batched_mlp"]["physics"] = figures(
                 lab0[2], bufs[0]["states"]["accepted"].cpu().numpy()[lab0[0]], lab0[3])
@@ -326,7 +356,7 @@ def main():
         if not args.no_learned:
             mlp, info = train(velo, torch, "stress", args.stress_train, "stress", args.stress_val, 4096, sp,
                               args.epochs, dev)
-            wall, cfg = time_batched(velo, torch, sbufs, streams, sp, mlp, args.steps // 4, args.warmup)
+            wall, cfg, _ = time_batched(velo, torch, sbufs, streams, sp, mlp, args.steps // 4, args.warmup)
             stress["batched_mlp"] = dict(
                 value=round(args.steps // 4 * n_ev / wall, 1), training=info, autotuned=cfg,
                 physics=figures(slab[2], sbufs[0]["states"]["accepted"].cpu().numpy()[slab[0]], slab[3]))
@@ -352,7 +382,7 @@ def main():
         del uws
         torch.cuda.empty_cache()
         if not args.no_learned:
-            wall, cfg = time_batched(velo, torch, ubuf, ust, params, mlp_nominal, usteps, 1)
+            wall, cfg, _ = time_batched(velo, torch, ubuf, ust, params, mlp_nominal, usteps, 1)
             uneven["batched_mlp"] = dict(value=round(usteps * ub.n_events / wall, 1), autotuned=cfg)
         del ubuf
         torch.cuda.empty_cache()
@@ -365,7 +395,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         import oracle
         threads = WORKERS
@@ -376,7 +406,14 @@ def main():
         dt = time.perf_counter() - t1
         cpu = dict(value=round(sample.n_events / dt, 1), unit="events/s", cores=threads, kind="oracle",
                    sample=f"first {sample.n_events} generated nominal events, cluster+find+fit, "
-                          f"{threads} threads over events, {dt:.2f} s wall")
+                          f"{threads} threads over events, {dt:.2f} s wall; the oracle is a correctness "
+                          f"reference (-O2, no contraction), not a tuned CPU implementation")
+        one = allb.range(0, min(500, allb.n_events))
+        t1 = time.perf_counter()
+        oracle.reconstruct(one.pixels, one.offsets, threads=1)
+        dt1 = time.perf_counter() - t1
+        cpu1 = dict(value=round(one.n_events / dt1, 1), unit="events/s", cores=1, kind="oracle",
+                    sample=f"first {one.n_events} generated nominal events, one thread, {dt1:.2f} s wall")
 
     out = dict(
         metric="VELO events/s on 1 MI355X (plain vs batched+MLP) at matched efficiency/ghosts",
@@ -387,6 +424,7 @@ def main():
                     form="plain" if args.no_learned else "batched_mlp",
                     pixels_per_event=round(per["px"] / E, 1)),
         roofline=roofline, stages=stages, forms=forms, stress=stress, uneven=uneven, cpu_baseline=cpu,
+        cpu_baseline_1thread=cpu1,
         gen_seconds=round(gen_s, 1),
     )
     print(json.dumps(out))
