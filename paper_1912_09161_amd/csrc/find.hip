@@ -208,10 +208,10 @@ struct FindScal {
 };
 
 // Staging of plane l.  RING tiers: the coordinates, bucket order and bucket
-// starts of the next plane are loaded into registers one step ahead (issue)
-// and stored into the ring table at the start of its step (commit), so the
-// global-memory latency overlaps a whole step.  Used flags and round winners
-// are cleared at commit.  Workspace tier: only those are cleared.
+// starts of plane l are loaded into registers at the start of step l+1
+// (issue) and stored into the ring table late in that step (commit), once
+// the seeds of step l+1 no longer read the slot's previous plane (l+3), so
+// the global-memory latency overlaps most of a step.
 template <int NT, typename IDX, bool RING>
 struct PlanePrefetch {
   static constexpr int PF = RING ? 4 : 1;            // hits per lane (capL <= 4 NT)
@@ -233,11 +233,14 @@ struct PlanePrefetch {
       }
     }
   }
+  // Coordinates, local indices and bucket starts only: the used flags and
+  // round winners of a plane are cleared at the start of its own step.  No
+  // barrier: the caller's next barrier publishes the table.
   template <typename MEM>
   __device__ __forceinline__ void commit(const EventIO& io, int l, const MEM& M) {
-    const uint32_t n = io.lnh[l];
-    const auto t = M.layer(io, l);
     if constexpr (RING) {
+      const uint32_t n = io.lnh[l];
+      const auto t = M.layer(io, l);
       float* hx = const_cast<float*>(t.hx);
       float* hy = const_cast<float*>(t.hy);
       IDX* kr = const_cast<IDX*>(t.kr);
@@ -245,19 +248,14 @@ struct PlanePrefetch {
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        if (i < n) {
-          hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; t.used[i] = 0; t.best[i] = CandSlot<RING>::kFree;
-        }
+        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; }
       }
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
         const uint32_t b = threadIdx.x + k * NT;
         if (b <= kNB) bsd[b] = bs[k];
       }
-    } else {
-      for (uint32_t i = threadIdx.x; i < n; i += NT) { t.used[i] = 0; t.best[i] = CandSlot<RING>::kFree; }
     }
-    wg_barrier<RING>();
   }
 };
 
@@ -328,6 +326,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
   };
   PlanePrefetch<NT, IDX, RING> pf;
   pf.issue(io, kLayers - 1, M.capL);
+  pf.commit(io, kLayers - 1, M);
   wg_barrier<RING>();
   const auto A = M.T;
   using SLOT = typename CandSlot<RING>::T;
@@ -338,12 +337,13 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     else return lda(slot) == k;
   };
   for (int l = kLayers - 1; l >= 0; --l) {
-    pf.commit(io, l, M);
     if (l > 0) pf.issue(io, l - 1, M.capL);
     const auto T0 = M.layer(io, l);
     const uint32_t base0 = io.lstart[l];
     const float zl = zt[l];
     const uint32_t n_act = sc.n_act;
+    // plane l enters its step: no hit used, no round winner
+    for (uint32_t i = tid; i < io.lnh[l]; i += NT) { T0.used[i] = 0; T0.best[i] = CandSlot<RING>::kFree; }
 
     // ---- 1. extend active tracks into plane l ----
     // (the seed counters were last read a step ago, several barriers back)
@@ -366,174 +366,182 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         }
       }
     };
-    // Big events (the middle and large tiers) have long windows of uneven length:
-    // there the (track, hit) pairs are balanced over the lanes; small events
-    // scan each track's window in its own lane.
-    if constexpr (RING && NT >= 512) {
-      // (a) window of every active track, prefix of the window sizes
-      uint32_t carry = 0;
-      for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
-        const uint32_t t = b0 + tid;
-        uint32_t cnt = 0;
-        if (t < n_act) {
+    if (n_act > 0) {
+      // Big events (the middle and large tiers) have long windows of uneven length:
+      // there the (track, hit) pairs are balanced over the lanes; small events
+      // scan each track's window in its own lane.
+      if constexpr (RING && NT >= 512) {
+        // (a) window of every active track, prefix of the window sizes
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
+          const uint32_t t = b0 + tid;
+          uint32_t cnt = 0;
+          if (t < n_act) {
+            A.tmatch[t] = kNone;
+            A.tbest[t] = kFree;
+            float xp, yp;
+            extrap(t, xp, yp);
+            const Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
+            const uint32_t s0 = T0.bstart[r.b0], l0 = T0.bstart[r.b1 + 1] - s0;
+            uint32_t s1 = 0, l1 = 0;
+            if (r.b2 <= r.b3) { s1 = T0.bstart[r.b2]; l1 = T0.bstart[r.b3 + 1] - s1; }
+            M.tw0[t] = s0 | (l0 << 16);
+            M.tw1[t] = s1 | (l1 << 16);
+            cnt = l0 + l1;
+          }
+          uint32_t tot;
+          const uint32_t ex = scan(cnt, &tot);
+          if (t < n_act) M.twp[t] = carry + ex;
+          carry += tot;
+        }
+        if (tid == 0) M.twp[n_act] = carry;
+        wg_barrier<RING>();
+        // (b) all (track, hit) pairs, split evenly over the lanes in contiguous
+        // chunks; four pairs of one track per step, their loads issued together
+        const uint32_t total = carry, per = (total + NT - 1) / NT;
+        uint32_t j = tid * per;
+        const uint32_t jend = j + per < total ? j + per : total;
+        if (j < jend) {
+          uint32_t lo = 0, hi = n_act - 1;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (M.twp[mid] <= j) lo = mid; else hi = mid - 1;
+          }
+          for (uint32_t t = lo; j < jend; ++t) {
+            const uint32_t wb = M.twp[t], we = M.twp[t + 1];
+            if (we <= j) continue;
+            const uint32_t w0 = M.tw0[t], w1 = M.tw1[t], l0 = w0 >> 16, key0 = A.key0[t];
+            float xp, yp;
+            extrap(t, xp, yp);
+            const uint32_t stop = we < jend ? we : jend;
+            for (uint32_t g = j; g < stop; g += 4) {
+              uint32_t ph[4];
+              float xh[4], yh[4];
+  #pragma unroll
+              for (uint32_t q = 0; q < 4; ++q) {
+                const uint32_t k = (g + q < stop ? g + q : stop - 1) - wb;
+                ph[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
+                xh[q] = T0.hx[ph[q]];
+                yh[q] = T0.hy[ph[q]];
+              }
+  #pragma unroll
+              for (uint32_t q = 0; q < 4; ++q) {
+                if (g + q >= stop) continue;
+                const float dx = xh[q] - xp, dy = yh[q] - yp;
+                const float s = dx * dx + dy * dy;
+                if (s <= P.s_fwd) add_ext(t, key0, ph[q], s);
+              }
+            }
+            j = stop;
+          }
+        }
+      } else {
+        for (uint32_t t = tid; t < n_act; t += NT) {
           A.tmatch[t] = kNone;
           A.tbest[t] = kFree;
+          const uint32_t key0 = A.key0[t];
           float xp, yp;
           extrap(t, xp, yp);
-          const Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
-          const uint32_t s0 = T0.bstart[r.b0], l0 = T0.bstart[r.b1 + 1] - s0;
-          uint32_t s1 = 0, l1 = 0;
-          if (r.b2 <= r.b3) { s1 = T0.bstart[r.b2]; l1 = T0.bstart[r.b3 + 1] - s1; }
-          M.tw0[t] = s0 | (l0 << 16);
-          M.tw1[t] = s1 | (l1 << 16);
-          cnt = l0 + l1;
+          Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
+          scan_window(T0, r, [&](uint32_t h, float xh, float yh) {
+            const float dx = xh - xp, dy = yh - yp;
+            const float s = dx * dx + dy * dy;
+            if (s <= P.s_fwd) add_ext(t, key0, h, s);
+          });
         }
-        uint32_t tot;
-        const uint32_t ex = scan(cnt, &tot);
-        if (t < n_act) M.twp[t] = carry + ex;
-        carry += tot;
       }
-      if (tid == 0) M.twp[n_act] = carry;
       wg_barrier<RING>();
-      // (b) all (track, hit) pairs, split evenly over the lanes in contiguous
-      // chunks; four pairs of one track per step, their loads issued together
-      const uint32_t total = carry, per = (total + NT - 1) / NT;
-      uint32_t j = tid * per;
-      const uint32_t jend = j + per < total ? j + per : total;
-      if (j < jend) {
-        uint32_t lo = 0, hi = n_act - 1;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if (M.twp[mid] <= j) lo = mid; else hi = mid - 1;
-        }
-        for (uint32_t t = lo; j < jend; ++t) {
-          const uint32_t wb = M.twp[t], we = M.twp[t + 1];
-          if (we <= j) continue;
-          const uint32_t w0 = M.tw0[t], w1 = M.tw1[t], l0 = w0 >> 16, key0 = A.key0[t];
-          float xp, yp;
-          extrap(t, xp, yp);
-          const uint32_t stop = we < jend ? we : jend;
-          for (uint32_t g = j; g < stop; g += 4) {
-            uint32_t ph[4];
-            float xh[4], yh[4];
-#pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-              const uint32_t k = (g + q < stop ? g + q : stop - 1) - wb;
-              ph[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
-              xh[q] = T0.hx[ph[q]];
-              yh[q] = T0.hy[ph[q]];
-            }
-#pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-              if (g + q >= stop) continue;
-              const float dx = xh[q] - xp, dy = yh[q] - yp;
-              const float s = dx * dx + dy * dy;
-              if (s <= P.s_fwd) add_ext(t, key0, ph[q], s);
-            }
-          }
-          j = stop;
+      {
+        const uint32_t nc = sc.ncf;
+        if (nc > VELO_MAX_CANDIDATES) return 2u;
+        if (nc > M.capC) return 1u;
+        if (nc > 0) {
+          // greedy matching by (s, first-hit key of the track, hit key)
+          auto less_hit = [&](uint32_t i, uint32_t j) {
+            const Cand ci = M.cand[i], cj = M.cand[j];
+            if (ci.s != cj.s) return ci.s < cj.s;
+            return A.key0[ci.a] < A.key0[cj.a];
+          };
+          auto less_trk = [&](uint32_t i, uint32_t j) {
+            const Cand ci = M.cand[i], cj = M.cand[j];
+            if (ci.s != cj.s) return ci.s < cj.s;
+            return T0.kr[ci.b] < T0.kr[cj.b];
+          };
+          // (track, hit) of candidate k
+          auto th = [&](uint32_t k, uint32_t& t, uint32_t& h) {
+            if constexpr (RING) { const uint32_t v = M.cpos[k]; t = v & kPosMask; h = v >> kPosBits; }
+            else { const Cand c = M.cand[k]; t = c.a; h = c.b; }
+          };
+          auto live = [&](uint32_t t, uint32_t h) { return A.tmatch[t] == kNone && !T0.used[h]; };
+          greedy_rounds<RING>(
+              nc, sc,
+              [&] {
+                for (uint32_t k = tid; k < nc; k += NT) {
+                  uint32_t t, h;
+                  th(k, t, h);
+                  if (!live(t, h)) continue;
+                  if constexpr (RING) {
+                    const uint64_t pr = M.cprio[k];
+                    atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)pr);
+                    atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)pr);
+                  } else {
+                    cas_min(T0.best + h, k, less_hit);
+                    cas_min(A.tbest + t, k, less_trk);
+                  }
+                }
+              },
+              [&] {
+                for (uint32_t k = tid; k < nc; k += NT) {
+                  uint32_t t, h;
+                  th(k, t, h);
+                  if (live(t, h) && holds(T0.best + h, k) && holds(A.tbest + t, k)) {
+                    A.tmatch[t] = h;
+                    T0.used[h] = 1;
+                  }
+                }
+              },
+              [&] {
+                bool any = false;
+                for (uint32_t k = tid; k < nc; k += NT) {
+                  uint32_t t, h;
+                  th(k, t, h);
+                  T0.best[h] = kFree;
+                  A.tbest[t] = kFree;
+                  if (live(t, h)) any = true;
+                }
+                return any;
+              });
         }
       }
-    } else {
+      // apply: append matched hits, count misses
       for (uint32_t t = tid; t < n_act; t += NT) {
-        A.tmatch[t] = kNone;
-        A.tbest[t] = kFree;
-        const uint32_t key0 = A.key0[t];
-        float xp, yp;
-        extrap(t, xp, yp);
-        Ranges r = window(pangle(xp, yp), point_window(xp, yp, P.rho_fwd), kNB);
-        scan_window(T0, r, [&](uint32_t h, float xh, float yh) {
-          const float dx = xh - xp, dy = yh - yp;
-          const float s = dx * dx + dy * dy;
-          if (s <= P.s_fwd) add_ext(t, key0, h, s);
-        });
+        const uint32_t h = A.tmatch[t];
+        if (h != kNone) {
+          const uint32_t nn = A.n[t];
+          io.hit_idx[26ull * A.slot[t] + nn] = base0 + (uint32_t)T0.kr[h];
+          const float xh = T0.hx[h], yh = T0.hy[h];
+          const float dz = zl - zt[A.la[t]];
+          A.tx[t] = (xh - A.xa[t]) / dz;
+          A.ty[t] = (yh - A.ya[t]) / dz;
+          A.xa[t] = xh;
+          A.ya[t] = yh;
+          A.la[t] = (uint8_t)l;
+          A.n[t] = (uint8_t)(nn + 1);
+          A.skip[t] = 0;
+        } else {
+          const int sk = A.skip[t] + 1;
+          A.skip[t] = (uint8_t)sk;
+          if (sk > P.max_skip) io.nhits[A.slot[t]] = A.n[t];
+        }
       }
     }
-    wg_barrier<RING>();
-    {
-      const uint32_t nc = sc.ncf;
-      if (nc > VELO_MAX_CANDIDATES) return 2u;
-      if (nc > M.capC) return 1u;
-      if (nc > 0) {
-        // greedy matching by (s, first-hit key of the track, hit key)
-        auto less_hit = [&](uint32_t i, uint32_t j) {
-          const Cand ci = M.cand[i], cj = M.cand[j];
-          if (ci.s != cj.s) return ci.s < cj.s;
-          return A.key0[ci.a] < A.key0[cj.a];
-        };
-        auto less_trk = [&](uint32_t i, uint32_t j) {
-          const Cand ci = M.cand[i], cj = M.cand[j];
-          if (ci.s != cj.s) return ci.s < cj.s;
-          return T0.kr[ci.b] < T0.kr[cj.b];
-        };
-        // (track, hit) of candidate k
-        auto th = [&](uint32_t k, uint32_t& t, uint32_t& h) {
-          if constexpr (RING) { const uint32_t v = M.cpos[k]; t = v & kPosMask; h = v >> kPosBits; }
-          else { const Cand c = M.cand[k]; t = c.a; h = c.b; }
-        };
-        auto live = [&](uint32_t t, uint32_t h) { return A.tmatch[t] == kNone && !T0.used[h]; };
-        greedy_rounds<RING>(
-            nc, sc,
-            [&] {
-              for (uint32_t k = tid; k < nc; k += NT) {
-                uint32_t t, h;
-                th(k, t, h);
-                if (!live(t, h)) continue;
-                if constexpr (RING) {
-                  const uint64_t pr = M.cprio[k];
-                  atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)pr);
-                  atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)pr);
-                } else {
-                  cas_min(T0.best + h, k, less_hit);
-                  cas_min(A.tbest + t, k, less_trk);
-                }
-              }
-            },
-            [&] {
-              for (uint32_t k = tid; k < nc; k += NT) {
-                uint32_t t, h;
-                th(k, t, h);
-                if (live(t, h) && holds(T0.best + h, k) && holds(A.tbest + t, k)) {
-                  A.tmatch[t] = h;
-                  T0.used[h] = 1;
-                }
-              }
-            },
-            [&] {
-              bool any = false;
-              for (uint32_t k = tid; k < nc; k += NT) {
-                uint32_t t, h;
-                th(k, t, h);
-                T0.best[h] = kFree;
-                A.tbest[t] = kFree;
-                if (live(t, h)) any = true;
-              }
-              return any;
-            });
-      }
+    // (no barrier: seeding touches neither the track table nor what the
+    // matching changed since its last round's barrier; the workspace tier's
+    // seed loop reads plane l's flags at once, so it needs the step-start
+    // clearing published when no extension phase did)
+    if constexpr (!RING) {
+      if (n_act == 0) wg_barrier<RING>();
     }
-    // apply: append matched hits, count misses
-    for (uint32_t t = tid; t < n_act; t += NT) {
-      const uint32_t h = A.tmatch[t];
-      if (h != kNone) {
-        const uint32_t nn = A.n[t];
-        io.hit_idx[26ull * A.slot[t] + nn] = base0 + (uint32_t)T0.kr[h];
-        const float xh = T0.hx[h], yh = T0.hy[h];
-        const float dz = zl - zt[A.la[t]];
-        A.tx[t] = (xh - A.xa[t]) / dz;
-        A.ty[t] = (yh - A.ya[t]) / dz;
-        A.xa[t] = xh;
-        A.ya[t] = yh;
-        A.la[t] = (uint8_t)l;
-        A.n[t] = (uint8_t)(nn + 1);
-        A.skip[t] = 0;
-      } else {
-        const int sk = A.skip[t] + 1;
-        A.skip[t] = (uint8_t)sk;
-        if (sk > P.max_skip) io.nhits[A.slot[t]] = A.n[t];
-      }
-    }
-    wg_barrier<RING>();
 
     // ---- 2. seeds on planes (l+2, l+1, l) ----
     uint32_t n_new = 0;
@@ -751,6 +759,9 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         wg_barrier<RING>();
       }
     }
+
+    // stage plane l-1 into the slot of plane l+2, which the seeds no longer read
+    if (l > 0) pf.commit(io, l - 1, M);
 
     // ---- 3. active table: surviving tracks compacted in place, then new seeds ----
     // Every lane reads its entry before the scan's barrier and writes after it;
