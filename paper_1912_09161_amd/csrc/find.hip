@@ -766,68 +766,85 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     // ---- 3. active table: surviving tracks compacted in place, then new seeds ----
     // Every lane reads its entry before the scan's barrier and writes after it;
     // entries only move down, and a chunk writes below the entries of later chunks.
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
-      const uint32_t t = b0 + tid;
-      const bool keep = t < n_act && (int)A.skip[t] <= P.max_skip;
-      uint32_t f_slot = 0, f_key0 = 0;
-      float f_xa = 0, f_ya = 0, f_tx = 0, f_ty = 0;
-      uint8_t f_la = 0, f_n = 0, f_skip = 0;
-      if (keep) {
-        f_slot = A.slot[t]; f_key0 = A.key0[t]; f_xa = A.xa[t]; f_ya = A.ya[t];
-        f_tx = A.tx[t]; f_ty = A.ty[t]; f_la = A.la[t]; f_n = A.n[t]; f_skip = A.skip[t];
+    const bool seeds = l <= kLayers - 3 && sc.ncs > 0;
+    const uint32_t created = sc.n_created;  // read before any scan barrier (updated at the step end)
+    // a new track from the accepted seed of h0 (local index i0 on plane l+2)
+    auto create = [&](uint32_t i0, uint32_t k, uint32_t rank, uint32_t n_keep) {
+      uint32_t cb, cc;
+      if constexpr (RING) {
+        const uint32_t v = M.cpos[k];
+        cb = (v >> kPosBits) & kPosMask; cc = (v >> (2 * kPosBits)) & kPosMask;
+      } else {
+        const Cand c = M.cand[k]; cb = c.b; cc = c.c;
       }
+      const uint32_t slot = (uint32_t)io.slot_base + created + rank;
+      uint32_t* hi = io.hit_idx + 26ull * slot;
+      hi[0] = io.lstart[l + 2] + i0;
+      hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[cb];
+      hi[2] = base0 + (uint32_t)T0.kr[cc];
+      const uint32_t pos = n_keep + rank;
+      if (pos < M.capT) {
+        const float x1 = T1.hx[cb], y1 = T1.hy[cb], x2 = T0.hx[cc], y2 = T0.hy[cc];
+        const float dz = zl - zt[l + 1];
+        A.slot[pos] = slot;
+        A.key0[pos] = ((uint32_t)(l + 2) << M.KSH) | i0;
+        A.xa[pos] = x2;
+        A.ya[pos] = y2;
+        A.tx[pos] = (x2 - x1) / dz;
+        A.ty[pos] = (y2 - y1) / dz;
+        A.la[pos] = (uint8_t)l;
+        A.n[pos] = 3;
+        A.skip[pos] = 0;
+      }
+    };
+    struct Keep { uint32_t slot, key0; float xa, ya, tx, ty; uint8_t la, n, skip; };
+    auto read_keep = [&](uint32_t t) {
+      return Keep{A.slot[t], A.key0[t], A.xa[t], A.ya[t], A.tx[t], A.ty[t], A.la[t], A.n[t], A.skip[t]};
+    };
+    auto write_keep = [&](uint32_t pos, const Keep& f) {
+      A.slot[pos] = f.slot; A.key0[pos] = f.key0; A.xa[pos] = f.xa; A.ya[pos] = f.ya;
+      A.tx[pos] = f.tx; A.ty[pos] = f.ty; A.la[pos] = f.la; A.n[pos] = f.n; A.skip[pos] = f.skip;
+    };
+    uint32_t n_keep;
+    if (n_act <= NT && (!seeds || n2 <= NT)) {
+      // one scan for both: survivors in the low half-word, new tracks in the high
+      const bool keep = tid < n_act && (int)A.skip[tid] <= P.max_skip;
+      Keep f{};
+      if (keep) f = read_keep(tid);
+      const uint32_t i0 = seeds && tid < n2 ? n2 - 1 - tid : kNone;
+      const SLOT kk = i0 != kNone ? T2.best[i0] : kFree;
       uint32_t tot;
-      const uint32_t pos = carry + scan(keep ? 1u : 0u, &tot);
-      if (keep) {
-        A.slot[pos] = f_slot; A.key0[pos] = f_key0; A.xa[pos] = f_xa; A.ya[pos] = f_ya;
-        A.tx[pos] = f_tx; A.ty[pos] = f_ty; A.la[pos] = f_la; A.n[pos] = f_n; A.skip[pos] = f_skip;
-      }
-      carry += tot;
-    }
-    const uint32_t n_keep = carry;
-    if (l <= kLayers - 3 && sc.ncs > 0) {
-      // seeds in decreasing key of h0 (decreasing local index on plane l+2)
-      const uint32_t created = sc.n_created;
-      uint32_t c2 = 0;
-      for (uint32_t b0 = 0; b0 < n2; b0 += NT) {
-        const uint32_t i0 = b0 + tid < n2 ? n2 - 1 - (b0 + tid) : kNone;
-        const SLOT kk = i0 != kNone ? T2.best[i0] : kFree;
+      const uint32_t ex = scan((keep ? 1u : 0u) | (kk != kFree ? 0x10000u : 0u), &tot);
+      n_keep = tot & 0xFFFFu;
+      n_new = tot >> 16;
+      if (keep) write_keep(ex & 0xFFFFu, f);
+      if (kk != kFree) create(i0, (uint32_t)kk, ex >> 16, n_keep);
+    } else {
+      uint32_t carry = 0;
+      for (uint32_t b0 = 0; b0 < n_act; b0 += NT) {
+        const uint32_t t = b0 + tid;
+        const bool keep = t < n_act && (int)A.skip[t] <= P.max_skip;
+        Keep f{};
+        if (keep) f = read_keep(t);
         uint32_t tot;
-        const uint32_t rank = c2 + scan(kk != kFree ? 1u : 0u, &tot);
-        if (kk != kFree) {
-          const uint32_t k = (uint32_t)kk;
-          uint32_t ca, cb, cc;
-          if constexpr (RING) {
-            const uint32_t v = M.cpos[k];
-            ca = v & kPosMask; cb = (v >> kPosBits) & kPosMask; cc = (v >> (2 * kPosBits)) & kPosMask;
-          } else {
-            const Cand c = M.cand[k]; ca = c.a; cb = c.b; cc = c.c;
-          }
-          (void)ca;
-          const uint32_t slot = (uint32_t)io.slot_base + created + rank;
-          uint32_t* hi = io.hit_idx + 26ull * slot;
-          hi[0] = io.lstart[l + 2] + i0;
-          hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[cb];
-          hi[2] = base0 + (uint32_t)T0.kr[cc];
-          const uint32_t pos = n_keep + rank;
-          if (pos < M.capT) {
-            const float x1 = T1.hx[cb], y1 = T1.hy[cb], x2 = T0.hx[cc], y2 = T0.hy[cc];
-            const float dz = zl - zt[l + 1];
-            A.slot[pos] = slot;
-            A.key0[pos] = ((uint32_t)(l + 2) << M.KSH) | i0;
-            A.xa[pos] = x2;
-            A.ya[pos] = y2;
-            A.tx[pos] = (x2 - x1) / dz;
-            A.ty[pos] = (y2 - y1) / dz;
-            A.la[pos] = (uint8_t)l;
-            A.n[pos] = 3;
-            A.skip[pos] = 0;
-          }
-        }
-        c2 += tot;
+        const uint32_t pos = carry + scan(keep ? 1u : 0u, &tot);
+        if (keep) write_keep(pos, f);
+        carry += tot;
       }
-      n_new = c2;
+      n_keep = carry;
+      if (seeds) {
+        // seeds in decreasing key of h0 (decreasing local index on plane l+2)
+        uint32_t c2 = 0;
+        for (uint32_t b0 = 0; b0 < n2; b0 += NT) {
+          const uint32_t i0 = b0 + tid < n2 ? n2 - 1 - (b0 + tid) : kNone;
+          const SLOT kk = i0 != kNone ? T2.best[i0] : kFree;
+          uint32_t tot;
+          const uint32_t rank = c2 + scan(kk != kFree ? 1u : 0u, &tot);
+          if (kk != kFree) create(i0, (uint32_t)kk, rank, n_keep);
+          c2 += tot;
+        }
+        n_new = c2;
+      }
     }
     if (n_keep + n_new > M.capT) return 1u;
     if (tid == 0) { sc.n_act = n_keep + n_new; sc.n_created += n_new; sc.ncf = 0; }
