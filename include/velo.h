@@ -240,17 +240,23 @@ velo_status velo_mlp_adam_step(float* d_params, float* d_m, float* d_v, const fl
 velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n, float* d_logit,
                            hipStream_t stream);
 
-/* Batched form.  Events of very uneven occupancy in one launch sequence:
-   the (event, plane) segments and the events are ordered by size, largest
-   first, on the device; clustering and track finding run as persistent
-   workgroups that take items from device counters in that order (work
-   stealing); the whole pipeline is captured once as a HIP graph and replayed
-   while the call's buffers, sizes and parameters stay the same.  On the
-   first call the context autotunes the launch shapes (workgroup sizes and
-   counts of each stage) by timing candidates on that call's batch; that call
-   synchronises the stream.  Results are identical to velo_reconstruct
-   (mlp == NULL) or velo_reconstruct_mlp.  The context owns the tuned
-   configuration and the graph; one context serves one stream at a time.   */
+/* Batched form.  Events of very uneven occupancy in one launch sequence.
+   On the first call the context autotunes the launch shapes stage by stage
+   (clustering: one workgroup per (event, plane) segment or a persistent grid
+   of some size; track finding: lanes per event, one workgroup per event or a
+   persistent grid; fit: lanes per workgroup) by timing candidates on that
+   call's batch; that call synchronises the stream.  Persistent grids take
+   their items from device counters in descending size order (the orders are
+   built on the device, only for the stages that use them: work stealing).
+   The pipeline of a call is captured as a HIP graph and replayed on later
+   calls with the same buffers, sizes, parameters and stream (the context
+   keeps the 32 most recently used graphs).  Results are identical to
+   velo_reconstruct (mlp == NULL) or velo_reconstruct_mlp.  On a stream the
+   caller is capturing, the call only enqueues the pipeline into the caller's
+   graph with the context's current shapes (no tuning, no graph of its own).
+   The context owns the tuned configuration and the graphs; calls on one
+   context must not overlap (one host thread at a time).  d_ws:
+   velo_batched_workspace_bytes bytes.                                      */
 typedef struct velo_context velo_context;
 velo_status velo_context_create(velo_context** ctx);
 void velo_context_destroy(velo_context* ctx);

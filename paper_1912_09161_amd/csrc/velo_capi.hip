@@ -234,6 +234,11 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
   c.ws = d_ws;
   c.ws_bytes = ws_bytes;
   hipError_t e;
+  // a stream the caller is capturing: enqueue into the caller's graph with the
+  // current shapes (no tuning, which synchronises, and no graph of our own)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (stream != nullptr && hipStreamIsCapturing(stream, &cs) != hipSuccess) return VELO_ERR_HIP;
+  if (cs != hipStreamCaptureStatusNone) return hip_status(velo::enqueue_batched(c, ctx->cfg, stream));
   if (!ctx->tuned) {
     if ((e = velo::autotune(ctx, c, stream)) != hipSuccess) return VELO_ERR_HIP;
     drop_graphs(ctx);
@@ -262,7 +267,8 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
   g.graph = nullptr;
   g.exec = nullptr;
   if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-    ctx->n_graphs = slot;  // drop the empty slot
+    g = ctx->graphs[ctx->n_graphs - 1];  // drop the empty slot
+    ctx->n_graphs--;
     return VELO_ERR_HIP;
   }
   const hipError_t le = velo::enqueue_batched(c, ctx->cfg, stream);

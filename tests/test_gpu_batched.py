@@ -66,3 +66,33 @@ def test_batched_equals_plain_and_replays(name, n, xl):
         _ = (px.to(torch.int64).sum() + r).item()
         same(host(bufs), ref, b)
     ctx.close()
+
+
+def test_batched_inside_a_caller_graph():
+    """A caller captures the (already tuned) batched call into its own graph:
+    the call only enqueues; every replay equals the plain form."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    b = generate("uneven", 400, workers=8)
+    P = velo.default_params()
+    ref = plain(b, P)
+    px, off = to_dev(b.pixels, b.offsets)
+    ctx = velo.Context()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bufs = ctx.reconstruct(px, off, params=P, stream=stream)  # tunes eagerly
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        ctx.reconstruct(px, off, params=P, bufs=bufs, stream=torch.cuda.current_stream())
+    for r in range(3):
+        for k in ("n_tracks", "nhits"):
+            bufs["tracks"][k].zero_()
+        bufs["hits"]["key"].zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = (px.to(torch.int64).sum() + r).item()
+        same(host(bufs), ref, b)
+    ctx.close()
