@@ -83,15 +83,40 @@ def parse():
 WORKERS = min(16, os.cpu_count() or 1)
 
 
-def to_device(velo, torch, batches, dev):
+def to_device(velo, torch, batches, dev, outputs=False):
+    """Inputs of every batch on the device (and an output set each if asked)."""
     bufs = []
     for b in batches:
         N, E = b.n_pixels, b.n_events
-        bufs.append(dict(px=torch.from_numpy(b.pixels.view(np.int32)).to(dev),
-                         off=torch.from_numpy(b.offsets.view(np.int64)).to(dev), N=N, E=E,
-                         hits=velo.alloc_hits(N, E, dev), tracks=velo.alloc_tracks(N, E, dev),
-                         states=velo.alloc_states(N, dev)))
+        B = dict(px=torch.from_numpy(b.pixels.view(np.int32)).to(dev),
+                 off=torch.from_numpy(b.offsets.view(np.int64)).to(dev), N=N, E=E)
+        if outputs:
+            B.update(alloc_out(velo, N, E, dev))
+        bufs.append(B)
     return bufs
+
+
+def alloc_out(velo, N, E, dev):
+    return dict(hits=velo.alloc_hits(N, E, dev), tracks=velo.alloc_tracks(N, E, dev),
+                states=velo.alloc_states(N, dev))
+
+
+def stream_outputs(velo, bufs, S, dev):
+    """One output set per stream, sized for the largest batch: steps in flight
+    on different streams never write the same buffer (a stream's steps run in
+    order); the input batches rotate over the streams."""
+    N, E = max(B["N"] for B in bufs), max(B["E"] for B in bufs)
+    return [alloc_out(velo, N, E, dev) for _ in range(S)]
+
+
+def clean_run(velo, torch, B, O, ws, params):
+    """One synchronous plain reconstruction of batch B into the output set O
+    (after the timed runs: the figures that read outputs come from here)."""
+    torch.cuda.synchronize()
+    velo.reconstruct(B["px"], B["off"], params=params, bufs=dict(hits=O["hits"], tracks=O["tracks"],
+                                                                 states=O["states"], ws=ws))
+    torch.cuda.synchronize()
+    return O
 
 
 def labels(B, b):
@@ -125,21 +150,21 @@ def repeats(run, steps, n_ev, n=10):
                 std=round(float(np.std(rates, ddof=1)), 1))
 
 
-def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_events=False, first=0):
+def time_plain(velo, torch, bufs, outs, streams, wss, params, steps, warmup, with_events=False, first=0):
     R, S = len(bufs), len(streams)
 
     def step(i, ev=None):
-        B = bufs[i % R]
-        st, ws = streams[i % S], wss[i % S]
+        B, k = bufs[i % R], i % S
+        st, ws, O = streams[k], wss[k], outs[k]
         if ev is not None:
             ev[0].record(st)
-        velo.cluster(B["px"], B["off"], hits=B["hits"], ws=ws, stream=st)
+        velo.cluster(B["px"], B["off"], hits=O["hits"], ws=ws, stream=st)
         if ev is not None:
             ev[1].record(st)
-        velo.find_tracks(B["hits"], B["off"], B["N"], params=params, tracks=B["tracks"], ws=ws, stream=st)
+        velo.find_tracks(O["hits"], B["off"], B["N"], params=params, tracks=O["tracks"], ws=ws, stream=st)
         if ev is not None:
             ev[2].record(st)
-        velo.fit(B["hits"], B["tracks"], B["off"], B["N"], params=params, states=B["states"], stream=st)
+        velo.fit(O["hits"], O["tracks"], B["off"], B["N"], params=params, states=O["states"], stream=st)
         if ev is not None:
             ev[3].record(st)
 
@@ -162,7 +187,7 @@ def time_plain(velo, torch, bufs, streams, wss, params, steps, warmup, with_even
     return max(wall, span), stage_ms / steps
 
 
-def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup, n_repeats=0):
+def time_batched(velo, torch, bufs, outs, streams, params, mlp, steps, warmup, n_repeats=0):
     R, S = len(bufs), len(streams)
     dev = bufs[0]["px"].device
     ctxs = [velo.Context() for _ in range(S)]
@@ -172,8 +197,9 @@ def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup, n_repea
     def step(i):
         B = bufs[i % R]
         k = i % S
+        O = outs[k]
         ctxs[k].reconstruct(B["px"], B["off"], params=params, mlp=mlp,
-                            bufs=dict(hits=B["hits"], tracks=B["tracks"], states=B["states"], ws=wss[k]),
+                            bufs=dict(hits=O["hits"], tracks=O["tracks"], states=O["states"], ws=wss[k]),
                             stream=streams[k])
 
     import math
@@ -190,7 +216,7 @@ def time_batched(velo, torch, bufs, streams, params, mlp, steps, warmup, n_repea
 
     wall = run(steps, 0)
     rep = repeats(run, steps, bufs[0]["E"], n_repeats) if n_repeats else None
-    step(0)  # leave batch 0's outputs from this form
+    step(0)  # leave batch 0's outputs from this form in the first stream's output set
     torch.cuda.synchronize()
     cfg = ctxs[0].config()
     for c in ctxs:
@@ -206,7 +232,7 @@ def train(velo, torch, train_cfg, n_train, val_cfg, n_val, val_first, params, ep
     t0 = time.time()
 
     def tracks_of(b):
-        B = to_device(velo, torch, [b], dev)[0]
+        B = to_device(velo, torch, [b], dev, outputs=True)[0]
         velo.reconstruct(B["px"], B["off"], params=params,
                          bufs=dict(hits=B["hits"], tracks=B["tracks"], states=B["states"],
                                    ws=velo.alloc_workspace(B["N"], B["E"], dev)))
@@ -268,26 +294,28 @@ def main():
     streams = [torch.cuda.Stream(dev) for _ in range(S)]
     params = velo.default_params()
     bufs = to_device(velo, torch, batches, dev)
+    outs = stream_outputs(velo, bufs, S, dev)
     max_px = max(B["N"] for B in bufs)
     wss = [velo.alloc_workspace(max_px, n_ev, dev) for _ in range(S)]
     torch.cuda.synchronize()
 
     # ---- plain form, stage boundaries marked with events on the launch streams
-    elapsed, stage_ms = time_plain(velo, torch, bufs, streams, wss, params, args.steps, args.warmup,
+    elapsed, stage_ms = time_plain(velo, torch, bufs, outs, streams, wss, params, args.steps, args.warmup,
                                    with_events=True)
     plain_value = args.steps * n_ev / elapsed
-    plain_rep = repeats(lambda n, first: time_plain(velo, torch, bufs, streams, wss, params, n, 0, first=first)[0],
-                        args.steps, n_ev)
+    plain_rep = repeats(lambda n, first: time_plain(velo, torch, bufs, outs, streams, wss, params, n, 0,
+                                                    first=first)[0], args.steps, n_ev)
 
     # algorithmic bytes per launch of each stage, from the batch contents
     tot = dict(px=0, hits=0, tracks=0, trk_hits=0)
     for B, b in zip(bufs, batches):
+        O = clean_run(velo, torch, B, outs[0], wss[0], params)
         tot["px"] += B["N"]
-        tot["hits"] += int(B["hits"]["n_hits"].sum().item())
-        nt = B["tracks"]["n_tracks"].cpu().numpy()
+        tot["hits"] += int(O["hits"]["n_hits"].sum().item())
+        nt = O["tracks"]["n_tracks"].cpu().numpy()
         tot["tracks"] += int(nt.sum())
         base = (b.offsets[:-1] // 3).astype(np.int64)
-        nhits = B["tracks"]["nhits"].cpu().numpy()
+        nhits = O["tracks"]["nhits"].cpu().numpy()
         idx = np.concatenate([base[e] + np.arange(nt[e]) for e in range(n_ev)])
         tot["trk_hits"] += int(nhits[idx].astype(np.int64).sum())
     per = {k: v / R for k, v in tot.items()}
@@ -317,9 +345,9 @@ def main():
                             repeats=plain_rep, hbm_overall=overall))
     lab0 = None
     if not args.no_physics:
-        lab0 = labels(bufs[0], batches[0])
-        forms["plain"]["physics"] = figures(lab0[2], bufs[0]["states"]["accepted"].cpu().numpy()[lab0[0]],
-                                            lab0[3])
+        O = clean_run(velo, torch, bufs[0], outs[0], wss[0], params)
+        lab0 = labels(O, batches[0])
+        forms["plain"]["physics"] = figures(lab0[2], O["states"]["accepted"].cpu().numpy()[lab0[0]], lab0[3])
 
     # ---- batched form with the learned classifier
     headline = plain_value
@@ -327,16 +355,16 @@ def main():
         mlp, info = train(velo, torch, "learn_train", args.train_events, "learn_val", args.val_events, 0,
                           params, args.epochs, dev)
         mlp_nominal = mlp
-        wall, cfg, brep = time_batched(velo, torch, bufs, streams, params, mlp, args.steps, args.warmup,
+        wall, cfg, brep = time_batched(velo, torch, bufs, outs, streams, params, mlp, args.steps, args.warmup,
                                        n_repeats=10)
         value = args.steps * n_ev / wall
         forms["batched_mlp"] = dict(value=round(value, 1), ms_per_step=round(wall * 1e3 / args.steps, 5),
                                     repeats=brep, training=info, autotuned=cfg)
         if lab0 is not None:
             forms["batched_mlp"]["physics"] = figures(
-                lab0[2], bufs[0]["states"]["accepted"].cpu().numpy()[lab0[0]], lab0[3])
+                lab0[2], outs[0]["states"]["accepted"].cpu().numpy()[lab0[0]], lab0[3])
         headline = value
-    del bufs, wss
+    del bufs, outs, wss
     torch.cuda.empty_cache()
 
     # ---- high-occupancy leg
@@ -346,23 +374,24 @@ def main():
         sb = generate("stress", n_ev * args.stress_batches, first_event=8192, workers=WORKERS)
         sbatches = [sb.range(i * n_ev, (i + 1) * n_ev) for i in range(args.stress_batches)]
         sbufs = to_device(velo, torch, sbatches, dev)
+        souts = stream_outputs(velo, sbufs, S, dev)
         swss = [velo.alloc_workspace(max(B["N"] for B in sbufs), n_ev, dev) for _ in range(S)]
-        sw, _ = time_plain(velo, torch, sbufs, streams, swss, sp, args.steps // 4, args.warmup)
+        sw, _ = time_plain(velo, torch, sbufs, souts, streams, swss, sp, args.steps // 4, args.warmup)
         stress = dict(workload=STRESS, batches=args.stress_batches,
                       plain=dict(value=round(args.steps // 4 * n_ev / sw, 1)))
-        slab = labels(sbufs[0], sbatches[0])
-        stress["plain"]["physics"] = figures(slab[2], sbufs[0]["states"]["accepted"].cpu().numpy()[slab[0]],
-                                             slab[3])
+        O = clean_run(velo, torch, sbufs[0], souts[0], swss[0], sp)
+        slab = labels(O, sbatches[0])
+        stress["plain"]["physics"] = figures(slab[2], O["states"]["accepted"].cpu().numpy()[slab[0]], slab[3])
         if not args.no_learned:
             mlp, info = train(velo, torch, "stress", args.stress_train, "stress", args.stress_val, 4096, sp,
                               args.epochs, dev)
-            wall, cfg, _ = time_batched(velo, torch, sbufs, streams, sp, mlp, args.steps // 4, args.warmup)
+            wall, cfg, _ = time_batched(velo, torch, sbufs, souts, streams, sp, mlp, args.steps // 4, args.warmup)
             stress["batched_mlp"] = dict(
                 value=round(args.steps // 4 * n_ev / wall, 1), training=info, autotuned=cfg,
-                physics=figures(slab[2], sbufs[0]["states"]["accepted"].cpu().numpy()[slab[0]], slab[3]))
+                physics=figures(slab[2], souts[0]["states"]["accepted"].cpu().numpy()[slab[0]], slab[3]))
             gp, gl = stress["plain"]["physics"]["ghost_rate"], stress["batched_mlp"]["physics"]["ghost_rate"]
             stress["ghost_rate_reduction"] = round(1 - gl / gp, 4) if gp > 0 else None
-        del sbufs, swss
+        del sbufs, souts, swss
         torch.cuda.empty_cache()
 
     # ---- uneven occupancy, the whole batch in one launch per stage / one graph
@@ -372,19 +401,20 @@ def main():
         ub = generate("uneven", args.uneven_events, workers=WORKERS)
         ugen = time.time() - t2
         ubuf = to_device(velo, torch, [ub], dev)
+        uouts = stream_outputs(velo, ubuf, 1, dev)
         uws = [velo.alloc_workspace(ubuf[0]["N"], ubuf[0]["E"], dev)]
         ust = streams[:1]
         usteps = max(3, args.steps // 100)
-        uw, _ = time_plain(velo, torch, ubuf, ust, uws, params, usteps, 1)
+        uw, _ = time_plain(velo, torch, ubuf, uouts, ust, uws, params, usteps, 1)
         uneven = dict(workload=UNEVEN, events=ub.n_events, pixels_per_event=round(ub.n_pixels / ub.n_events, 1),
                       steps=usteps, gen_seconds=round(ugen, 1),
                       plain=dict(value=round(usteps * ub.n_events / uw, 1)))
         del uws
         torch.cuda.empty_cache()
         if not args.no_learned:
-            wall, cfg, _ = time_batched(velo, torch, ubuf, ust, params, mlp_nominal, usteps, 1)
+            wall, cfg, _ = time_batched(velo, torch, ubuf, uouts, ust, params, mlp_nominal, usteps, 1)
             uneven["batched_mlp"] = dict(value=round(usteps * ub.n_events / wall, 1), autotuned=cfg)
-        del ubuf
+        del ubuf, uouts
         torch.cuda.empty_cache()
 
     if args.copy_mb > 0:

@@ -183,7 +183,11 @@ velo_status velo_find_tracks(const velo_hits* hits, const uint64_t* d_offsets, u
 /* Simple Kalman filter per projection, x and y independent, with multiple
    scattering noise for a constant transverse momentum pt0 (paper Sec. 2.3.1,
    third paragraph), then transport to the point of closest approach to the
-   beamline (fourth paragraph), chi2, ndof and the plain quality cut.       */
+   beamline (fourth paragraph), chi2, ndof and the plain quality cut.
+   Tracks given by the caller are checked, not trusted: a count above
+   floor((offsets[e+1] - offsets[e]) / 3) is clamped to it, and a slot whose
+   nhits is outside [3, 26] or whose hit_idx points outside its event is
+   skipped (its state is left as it was).                                    */
 velo_status velo_fit(const velo_hits* hits, const velo_tracks* tracks, const uint64_t* d_offsets,
                      uint32_t n_events, uint64_t n_pixels, const velo_params* params,
                      const velo_states* out, hipStream_t stream);

@@ -939,8 +939,7 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   __shared__ uint8_t s_used[3 * CAPL];
   __shared__ uint64_t s_best[3 * CAPL];
   __shared__ uint32_t s_bstart[3 * (kNB + 1)];
-  __shared__ uint32_t t_slot[CAPT], t_key0[CAPT], t_tmatch[CAPT];
-  __shared__ uint64_t t_tbest[CAPT];
+  __shared__ uint32_t t_slot[CAPT], t_key0[CAPT];
   __shared__ float t_xa[CAPT], t_ya[CAPT], t_tx[CAPT], t_ty[CAPT];
   __shared__ uint8_t t_la[CAPT], t_n[CAPT], t_skip[CAPT];
   // candidates (priorities, positions) share their space with the seed doublet
@@ -948,13 +947,21 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   // and extension candidates are dead before the windows are built
   constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u);
   __shared__ uint64_t s_cw[((kCandBytes > kWinBytes ? kCandBytes : kWinBytes) + 7u) / 8u];
-  __shared__ Dbl s_dbl[CAPD];
+  // the matches and round winners of the extension step share their space with
+  // the seed doublets: the doublets are written after the barrier that ends
+  // the first seeding phase (every match is applied by then) and are dead
+  // before the next step's extension phase
+  static_assert(CAPT % 2 == 0 && CAPD % 2 == 0, "8-byte alignment of the shared region");
+  constexpr uint32_t kTdBytes = 12u * CAPT > 4u * CAPD ? 12u * CAPT : 4u * CAPD;
+  __shared__ uint64_t s_td[kTdBytes / 8];
+  uint32_t* t_tmatch = reinterpret_cast<uint32_t*>(s_td);
+  uint64_t* t_tbest = s_td + CAPT / 2;
   __shared__ uint32_t s_tw[NT >= 512 ? 3 * CAPT + 1 : 1];  // balanced forward search only
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
   M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
-  M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = s_dbl; M.capD = CAPD;
+  M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
   M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
   M.T = TrackTab<uint64_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
   M.cand = nullptr;
@@ -1021,7 +1028,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
-constexpr uint32_t kSCapL = 320, kSCapT = 256, kSCapC = 384, kSCapD = 512;
+constexpr uint32_t kSCapL = 352, kSCapT = 288, kSCapC = 384, kSCapD = 3 * kSCapT;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(NT) void k_fit(const float* __restrict__ X,
   if (end < b || end > n_pixels) return;
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
-  const uint32_t nt = n_tracks[e];
+  const uint32_t nt = event_tracks(n_tracks[e], ne);
   for (uint32_t t = threadIdx.x; t < nt; t += NT) {
     const uint64_t slot = base + t;
     FitOut f;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
   if (end < b || end > n_pixels) return;
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
-  const uint32_t nt = n_tracks[e];
+  const uint32_t nt = event_tracks(n_tracks[e], ne);
   MlpWave& Wv = W[threadIdx.x >> 6];
   for (uint32_t t0 = 0; t0 < nt; t0 += NT) {
     const uint32_t t = t0 + threadIdx.x;

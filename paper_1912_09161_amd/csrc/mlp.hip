@@ -57,7 +57,8 @@ __global__ __launch_bounds__(128) void k_features(const uint32_t* __restrict__ k
   if (end < b || end > n_pixels) return;
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
-  for (uint32_t t = threadIdx.x; t < n_tracks[e]; t += 128) {
+  const uint32_t nt = event_tracks(n_tracks[e], ne);
+  for (uint32_t t = threadIdx.x; t < nt; t += 128) {
     const uint64_t slot = base + t;
     const int n = nhits[slot];
     if (n < 3 || n > kLayers) continue;

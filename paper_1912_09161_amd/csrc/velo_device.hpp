@@ -30,6 +30,14 @@ __device__ __forceinline__ uint32_t w_layer(uint32_t w) { return (w >> 22) & 31u
 __device__ __forceinline__ uint32_t w_charge(uint32_t w) { return (w >> 27) & 15u; }
 
 // inactive pixel: centre radius < 5.1 mm, in exact integer form
+// Track slots of an event with ne raw words: every track holds at least three
+// distinct hits and an event has at most ne hits, so a count above ne / 3
+// cannot come from the track finding and is clamped (the event's slots end
+// there; no slot of another event is touched).
+__device__ __forceinline__ uint32_t event_tracks(uint32_t n_tracks, uint32_t ne) {
+  return n_tracks < ne / 3 ? n_tracks : ne / 3;
+}
+
 __device__ __forceinline__ bool in_hole(uint32_t col, uint32_t row) {
   int dc = 2 * (int)col - 1535, dr = 2 * (int)row - 1535;
   return dc * dc + dr * dr <= 34393;

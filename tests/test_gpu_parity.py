@@ -8,7 +8,7 @@ plain-cut decisions, identical per-event status codes.
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_all, gpu_reconstruct
+from gpu_helpers import compare_all, gpu_reconstruct, to_dev
 from synth import generate
 from synth.raw import line_event, pack, shuffle_within_layers, word
 
@@ -115,3 +115,42 @@ def test_nominal_full_batch(orc):
     b = generate("nominal", 1000)
     g, o, (nh, nt, ns) = run_pair(orc, b.pixels, b.offsets)
     assert nt > 150000
+
+
+def test_fit_checks_caller_tracks():
+    """velo_fit on caller-edited tracks: an oversized track count is clamped to
+    the event's slots, slots with an invalid hit count or a hit outside the
+    event are skipped and keep their previous state; every other slot equals
+    the fit of the unedited tracks."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    b = generate("nominal", 20)
+    px, off = to_dev(b.pixels, b.offsets)
+    out = velo.reconstruct(px, off)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in out["states"].items()}
+    tr = {k: v.clone() for k, v in out["tracks"].items()}
+    o = b.offsets.astype(np.int64)
+    nt = tr["n_tracks"].cpu().numpy()
+    e = 3
+    base, cap = o[e] // 3, (o[e + 1] - o[e]) // 3
+    assert nt[e] >= 2 and cap > nt[e]
+    # slots after the event's real tracks hold no track; then a huge count
+    tr["nhits"][base + nt[e]:base + cap] = 0
+    tr["n_tracks"][e] = -16  # 0xFFFFFFF0
+    bad_n, bad_i = base, base + 1
+    tr["nhits"][bad_n] = 27
+    tr["hit_idx"][26 * bad_i + 1] = int(o[e + 1] - o[e])
+    st = {k: torch.full_like(v, 7) for k, v in ref.items()}
+    velo.fit(out["hits"], tr, off, b.n_pixels, states=st)
+    torch.cuda.synchronize()
+    for k in ("x", "y", "z", "tx", "ty", "chi2", "ndof", "accepted"):
+        g, r = st[k].cpu().numpy(), ref[k].cpu().numpy()
+        for ev in range(20):
+            sl = np.arange(o[ev] // 3, o[ev] // 3 + nt[ev])
+            if ev == e:
+                sl = sl[(sl != bad_n) & (sl != bad_i)]
+            np.testing.assert_array_equal(g[sl].view(np.uint8), r[sl].view(np.uint8), err_msg=k)
+        skipped = np.r_[bad_n, bad_i, np.arange(base + nt[e], base + cap)]
+        assert np.all(g[skipped] == 7), k
