@@ -17,9 +17,11 @@ value is the batched_mlp form.
 
 As in the paper's throughput protocol (Sec. 3.2: several CPU-thread / GPU-
 stream pairs, each with its own events), steps are issued round-robin on
-several HIP streams with their own workspaces, and they rotate over several
-distinct batches with their own outputs, so the 256 MB Infinity Cache cannot
-hold the working set.
+several HIP streams with their own workspaces and outputs, and they rotate
+over several distinct input batches, so the 256 MB Infinity Cache cannot hold
+the working set.  The process asks HIP for more hardware queues than it has
+streams (GPU_MAX_HW_QUEUES), so a stream waiting on a long kernel does not
+hold up another stream queued behind it on the same hardware queue.
 
 A second leg repeats both forms on high-occupancy events (the stress
 sample); a third times 100k events of uneven occupancy in one launch per
@@ -59,7 +61,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--events", type=int, default=1000, help="events per batch (one step)")
     ap.add_argument("--batches", type=int, default=8, help="distinct device-resident batches")
-    ap.add_argument("--streams", type=int, default=6, help="concurrent HIP streams")
+    ap.add_argument("--streams", type=int, default=12, help="concurrent HIP streams")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues HIP gives the process (GPU_MAX_HW_QUEUES, 1..32); more "
+                         "queues than streams, so that no two streams share one")
     ap.add_argument("--cpu-events", type=int, default=0,
                     help="oracle sample size (default: all generated nominal events)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -279,6 +284,11 @@ def main():
               "so several GPUs would each run this benchmark on their own share.", file=sys.stderr)
         sys.exit(2)
 
+    if not 1 <= args.hw_queues <= 32:
+        print("--hw-queues must be within 1..32", file=sys.stderr)
+        sys.exit(2)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)  # read when HIP initialises, below
+
     from synth import generate
     n_ev, R = args.events, args.batches
     t0 = time.time()
@@ -451,6 +461,7 @@ def main():
         ms_per_step=round(n_ev / headline * 1e3, 5), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload=WORKLOAD, events_per_step=n_ev, rotating_batches=R, streams=S,
+                    hw_queues=args.hw_queues,
                     form="plain" if args.no_learned else "batched_mlp",
                     pixels_per_event=round(per["px"] / E, 1)),
         roofline=roofline, stages=stages, forms=forms, stress=stress, uneven=uneven, cpu_baseline=cpu,

@@ -249,7 +249,10 @@ velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n,
    (clustering: one workgroup per (event, plane) segment or a persistent grid
    of some size; track finding: lanes per event, one workgroup per event or a
    persistent grid; fit: lanes per workgroup) by timing candidates on that
-   call's batch; that call synchronises the stream.  Persistent grids take
+   call's batch; that call synchronises the stream.  A persistent grid is
+   chosen only if it is at least 15 % faster than one workgroup per item on
+   the tuning stream (under several busy streams one workgroup per item
+   interleaves better with the other streams' work).  Persistent grids take
    their items from device counters in descending size order (the orders are
    built on the device, only for the stages that use them: work stealing).
    The pipeline of a call is captured as a HIP graph and replayed on later
@@ -266,8 +269,11 @@ velo_status velo_context_create(velo_context** ctx);
 void velo_context_destroy(velo_context* ctx);
 /* out6 = {tuned, clustering grid (0 = one workgroup per segment), large-segment
    grid, track-finding lanes per event, track-finding grid (0 = one workgroup
-   per event), fit lanes per event}; tuned_ms3 (may be NULL) = best stage times. */
-velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms3);
+   per event), fit lanes per event}; tuned_ms5 (may be NULL) = tuning-stream
+   times of the chosen clustering, track-finding and fit shapes, then the best
+   clustering time with one workgroup per segment and the best track-finding
+   time with one workgroup per event.                                       */
+velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms5);
 size_t velo_batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
 velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels,
                                      const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,

@@ -233,7 +233,7 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
 struct velo_context {
   bool tuned = false;
   velo::BatchedCfg cfg{2048, 512, 256, 1024, 128};
-  float tuned_ms[3] = {0, 0, 0};
+  float tuned_ms[5] = {0, 0, 0, 0, 0};
   // captured graphs of recent call shapes (buffers, sizes, parameters, stream)
   static constexpr int kGraphs = 32;
   struct Entry {
@@ -294,6 +294,13 @@ hipError_t time_stage(const velo::BatchedCall& c, const velo::BatchedCfg& k, int
 
 namespace velo {
 
+// A persistent grid is taken only if it beats one workgroup per item by this
+// factor on the tuning stream.  The tuner times one stream, while callers
+// often keep several streams busy; there one workgroup per item interleaves
+// with the other streams' kernels, whereas a persistent grid holds its slots
+// until its queue drains, so a small latency gain alone does not carry over.
+constexpr float kPersistentGain = 0.85f;
+
 // Pick the launch shapes stage by stage on the live batch: clustering first
 // (its output feeds the next stage), then track finding, then the fit.
 static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t s) {
@@ -304,32 +311,42 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
   {
     const uint32_t smalls[] = {0, 1024, 2048, 4096, 8192};
     const uint32_t mids[] = {256, 512, 1024};
-    float bt = 1e30f;
-    BatchedCfg k = best;
+    float bt[2] = {1e30f, 1e30f};  // one workgroup per segment, persistent
+    BatchedCfg k = best, pick[2] = {best, best};
     for (uint32_t sg : smalls)
       for (uint32_t mg : mids) {
         k.small_grid = sg;
         k.mid_grid = mg;
         if ((e = time_stage(c, k, 1, s, 3, &t)) != hipSuccess) return e;
-        if (t < bt) { bt = t; best.small_grid = sg; best.mid_grid = mg; }
+        const int p = sg != 0;
+        if (t < bt[p]) { bt[p] = t; pick[p] = k; }
       }
-    ctx->tuned_ms[0] = bt;
+    const int p = bt[1] < kPersistentGain * bt[0];
+    best.small_grid = pick[p].small_grid;
+    best.mid_grid = pick[p].mid_grid;
+    ctx->tuned_ms[0] = bt[p];
+    ctx->tuned_ms[3] = bt[0];
     if ((e = enqueue_batched(c, best, s, 1)) != hipSuccess) return e;
   }
   // track finding: lanes per event x (one workgroup per event | persistent grid)
   {
     const int threads[] = {128, 256};
     const uint32_t grids[] = {0, 512, 768, 1024, 1536};
-    float bt = 1e30f;
-    BatchedCfg k = best;
+    float bt[2] = {1e30f, 1e30f};  // one workgroup per event, persistent
+    BatchedCfg k = best, pick[2] = {best, best};
     for (int nt : threads)
       for (uint32_t g : grids) {
         k.find_threads = nt;
         k.find_grid = g;
         if ((e = time_stage(c, k, 2, s, 3, &t)) != hipSuccess) return e;
-        if (t < bt) { bt = t; best.find_threads = nt; best.find_grid = g; }
+        const int p = g != 0;
+        if (t < bt[p]) { bt[p] = t; pick[p] = k; }
       }
-    ctx->tuned_ms[1] = bt;
+    const int p = bt[1] < kPersistentGain * bt[0];
+    best.find_threads = pick[p].find_threads;
+    best.find_grid = pick[p].find_grid;
+    ctx->tuned_ms[1] = bt[p];
+    ctx->tuned_ms[4] = bt[0];
     if ((e = enqueue_batched(c, best, s, 2)) != hipSuccess) return e;
   }
   // fit: lanes per event

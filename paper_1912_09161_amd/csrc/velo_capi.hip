@@ -192,7 +192,7 @@ void velo_context_destroy(velo_context* ctx) {
   delete ctx;
 }
 
-velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms3) {
+velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms5) {
   if (!ctx || !out6) return VELO_ERR_ARG;
   out6[0] = ctx->tuned ? 1 : 0;
   out6[1] = (int32_t)ctx->cfg.small_grid;
@@ -200,8 +200,8 @@ velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* t
   out6[3] = ctx->cfg.find_threads;
   out6[4] = (int32_t)ctx->cfg.find_grid;
   out6[5] = ctx->cfg.fit_threads;
-  if (tuned_ms3)
-    for (int i = 0; i < 3; ++i) tuned_ms3[i] = ctx->tuned_ms[i];
+  if (tuned_ms5)
+    for (int i = 0; i < 5; ++i) tuned_ms5[i] = ctx->tuned_ms[i];
   return VELO_OK;
 }
 

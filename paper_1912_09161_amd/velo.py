@@ -370,10 +370,11 @@ class Context:
 
     def config(self) -> dict:
         out = (C.c_int32 * 6)()
-        ms = (C.c_float * 3)()
+        ms = (C.c_float * 5)()
         _check(lib().velo_context_config(self._h, out, ms))
         return dict(tuned=bool(out[0]), cluster_grid=out[1], mid_grid=out[2], find_threads=out[3],
-                    find_grid=out[4], fit_threads=out[5], tuned_ms=[float(v) for v in ms])
+                    find_grid=out[4], fit_threads=out[5], tuned_ms=[float(v) for v in ms[:3]],
+                    per_item_ms=[float(ms[3]), float(ms[4])])
 
     def reconstruct(self, pixels, offsets, params=None, mlp: Mlp | None = None, bufs=None, stream=None):
         E = offsets.numel() - 1
