@@ -25,10 +25,14 @@ hold up another stream queued behind it on the same hardware queue.
 
 A second leg repeats both forms on high-occupancy events (the stress
 sample); a third times 100k events of uneven occupancy in one launch per
-stage (plain) or one graph replay (batched), the batched form's use case.  Prints one JSON line: events/s of every form, the HBM roofline of
-the dominant stage (stage durations from HIP events recorded on the launch
-streams), physics figures of merit from generator truth, and the CPU oracle's
-throughput on a bounded sample of the nominal events.
+stage (plain) or one graph replay (batched), the batched form's use case.
+
+Prints one JSON line: events/s of every form; the HBM roofline of the
+dominant stage, with stage durations from HIP events recorded on the launch
+stream of a separate single-stream pass (with several streams a stage's span
+includes the other streams' kernels); physics figures of merit from
+generator truth; the CPU oracle's throughput on a bounded sample of the
+nominal events.
 """
 from __future__ import annotations
 
@@ -65,6 +69,8 @@ def parse():
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="hardware queues HIP gives the process (GPU_MAX_HW_QUEUES, 1..32); more "
                          "queues than streams, so that no two streams share one")
+    ap.add_argument("--stage-steps", type=int, default=48,
+                    help="steps of the single-stream pass that times each stage (roofline)")
     ap.add_argument("--cpu-events", type=int, default=0,
                     help="oracle sample size (default: all generated nominal events)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -310,11 +316,15 @@ def main():
     torch.cuda.synchronize()
 
     # ---- plain form, stage boundaries marked with events on the launch streams
-    elapsed, stage_ms = time_plain(velo, torch, bufs, outs, streams, wss, params, args.steps, args.warmup,
-                                   with_events=True)
+    elapsed, _ = time_plain(velo, torch, bufs, outs, streams, wss, params, args.steps, args.warmup)
     plain_value = args.steps * n_ev / elapsed
     plain_rep = repeats(lambda n, first: time_plain(velo, torch, bufs, outs, streams, wss, params, n, 0,
                                                     first=first)[0], args.steps, n_ev)
+
+    # stage durations: a pass on one stream with the GPU to itself (with several
+    # streams a stage's span on its stream includes the other streams' kernels)
+    _, stage_ms = time_plain(velo, torch, bufs, outs[:1], streams[:1], wss[:1], params, args.stage_steps, 2,
+                             with_events=True)
 
     # algorithmic bytes per launch of each stage, from the batch contents
     tot = dict(px=0, hits=0, tracks=0, trk_hits=0)
@@ -464,7 +474,8 @@ def main():
                     hw_queues=args.hw_queues,
                     form="plain" if args.no_learned else "batched_mlp",
                     pixels_per_event=round(per["px"] / E, 1)),
-        roofline=roofline, stages=stages, forms=forms, stress=stress, uneven=uneven, cpu_baseline=cpu,
+        roofline=roofline, stages=stages, stage_timing=f"one stream, {args.stage_steps} steps",
+        forms=forms, stress=stress, uneven=uneven, cpu_baseline=cpu,
         cpu_baseline_1thread=cpu1,
         gen_seconds=round(gen_s, 1),
     )

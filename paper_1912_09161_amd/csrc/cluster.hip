@@ -21,7 +21,7 @@
 
 namespace velo {
 
-constexpr uint32_t kSmallCap = 512;   // words per segment handled by one wave
+constexpr uint32_t kSmallCap = 448;   // words per segment handled by one wave
 constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
 static_assert(kMidCap >= (uint32_t)kPix, "the workspace row table lives at the segment's own positions");
 constexpr int kMidThreads = 256;
@@ -96,7 +96,8 @@ struct SegScratch {
   uint32_t* par;   // [n] bucket-order staging, then union-find parents
   uint32_t* qs;    // [n] per root: Q << 16 | N (PACKED) or Q
   uint32_t* ns;    // [n] per root: N (unused when PACKED)
-  uint64_t* scr;   // [n] per root: charge-weighted row sum << 32 | column sum
+  uint64_t* scr;   // [n] per root: charge-weighted row sum << 32 | column sum (may share
+                   // the row table's space: cleared after the row table's last use)
   uint32_t* tmp;   // NT/64 + 1 words of LDS (scans)
   uint32_t* flag;  // one word of LDS
 };
@@ -200,7 +201,6 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
     S.par[p] = p;
     S.qs[p] = 0;
     if constexpr (!PACKED) S.ns[p] = 0;
-    S.scr[p] = 0;
   }
   __syncthreads();
   // edges to (r, c+1) and (r+1, c-1..c+1)
@@ -217,6 +217,9 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
       }
     }
   }
+  __syncthreads();
+  // the row table is dead from here on (the sums may share its space)
+  for (uint32_t p = tid; p < n; p += NT) S.scr[p] = 0;
   __syncthreads();
   // integer sums at the roots
   for (uint32_t p = tid; p < n; p += NT) {
@@ -339,12 +342,15 @@ struct SmallArgs {
 };
 
 struct SmallLds {
-  uint32_t rows[kPix / 2];
+  // the row table and the cluster sums are never live together
+  union {
+    uint32_t rows[kPix / 2];
+    uint64_t scr[kSmallCap];
+  } rs;
   uint32_t srt[kSmallCap], par[kSmallCap], qs[kSmallCap];
-  uint64_t scr[kSmallCap];
   uint32_t tmp[2], flag;
   __device__ SegScratch<true> scratch() {
-    return SegScratch<true>{rows, srt, par, qs, nullptr, scr, tmp, &flag};
+    return SegScratch<true>{rs.rows, srt, par, qs, nullptr, rs.scr, tmp, &flag};
   }
 };
 
@@ -404,8 +410,9 @@ __global__ __launch_bounds__(kMidThreads) void k_mid(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ ws,
                                                      uint64_t* __restrict__ ws64, uint64_t n_pixels,
                                                      uint32_t* __restrict__ steal) {
-  __shared__ uint32_t rows[kPix / 2], srt[kMidCap], par[kMidCap], qs[kMidCap];
-  __shared__ uint64_t scr[kMidCap];
+  __shared__ uint64_t scr[kMidCap];  // its first kPix / 2 words also hold the row table
+  __shared__ uint32_t srt[kMidCap], par[kMidCap], qs[kMidCap];
+  uint32_t* rows = reinterpret_cast<uint32_t*>(scr);
   __shared__ uint32_t tmp[kMidThreads / kWave + 1], flag, item;
   const uint32_t count = *mid_count;
   // static round robin, or work stealing from a counter when `steal` is given
