@@ -193,10 +193,8 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
   if (stages & 1) {
     // clearing, validation, size ordering, clustering
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
-    hipLaunchKernelGGL(k_clear, dim3((c.n_events + 255) / 256), dim3(256), 0, s, c.hits.status,
-                       c.n_events, (uint32_t*)c.ws);
     hipLaunchKernelGGL(k_validate, dim3(c.n_events), dim3(kValThreads), 0, s, c.px, c.offsets,
-                       c.n_pixels, c.hits.status, c.hits.layer_start);
+                       c.n_pixels, c.hits.status, c.hits.layer_start, (uint32_t*)c.ws);
     // size orders for the persistent kernels that use them
     const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
     if (mode) {

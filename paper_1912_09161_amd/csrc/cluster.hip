@@ -4,9 +4,9 @@
 // here a region is one (event, plane) segment of the raw buffer).
 //
 // Pipeline (all on one stream, no host round trip):
-//   k_clear     status[e] = 0, work-list counter = 0
 //   k_validate  one workgroup per event: bad word / hole / plane-order flags
-//               and the plane boundaries (layer_start) of the event
+//               and the plane boundaries (layer_start) of the event; clears
+//               the large-segment work list
 //   k_small     one 64-lane workgroup per (event, plane) segment of at most
 //               kSmallCap words: LDS counting sort by address (row buckets,
 //               then rank inside the row), 8-neighbour union-find (roots =
@@ -262,30 +262,13 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
 
 // ---------------------------------------------------------------------------
 
-__global__ void k_clear(uint32_t* __restrict__ status, uint32_t n_events, uint32_t* __restrict__ counter) {
-  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n_events) status[e] = 0;
-  if (e == 0) *counter = 0;
-}
-
 constexpr int kValThreads = 256;
 constexpr uint32_t kValUnroll = 4;  // words in flight per lane
 
-// One workgroup per event: flags of every word and the plane boundaries of
-// the event (layer_start[27e + l] = index of the first word of plane >= l).
-// Events never share a word, so overlapping or inconsistent offsets of one
-// event cannot disturb another (inconsistent ones are flagged by k_finalize).
-__global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __restrict__ px,
-                                                          const uint64_t* __restrict__ offsets,
-                                                          uint64_t n_pixels,
-                                                          uint32_t* __restrict__ status,
-                                                          uint32_t* __restrict__ layer_start) {
-  const uint32_t e = blockIdx.x;
-  const uint64_t b = offsets[e], end = offsets[e + 1];
-  if (!(b <= end && end <= n_pixels)) return;
-  const uint32_t n = (uint32_t)(end - b);
-  const uint32_t* __restrict__ w = px + b;
-  uint32_t* ls = layer_start + 27ull * e;
+// Flags of the n words of one event (OR-ed into *flags, in LDS) and its plane
+// boundaries ls[0..26]; kValThreads lanes, kValUnroll words in flight per lane.
+__device__ __forceinline__ void validate_words(const uint32_t* __restrict__ w, uint32_t n,
+                                               uint32_t* __restrict__ ls, uint32_t* flags_out) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t flags = 0;
   for (uint32_t i0 = 0; i0 < n; i0 += kValThreads * kValUnroll) {
@@ -319,7 +302,32 @@ __global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __rest
         for (int l = (int)lc + 1; l <= 26; ++l) ls[l] = n;
     }
   }
-  if (flags) atomicOr(status + e, flags);
+  if (flags) atomicOr(flags_out, flags);
+}
+
+// One workgroup per event: flags of every word (status[e], written whole)
+// and the plane boundaries of the event (layer_start[27e + l] = index of the
+// first word of plane >= l); workgroup 0 also clears the large-segment list.
+// Events never share a word, so overlapping or inconsistent offsets of one
+// event cannot disturb another (inconsistent ones are flagged by k_finalize).
+__global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __restrict__ px,
+                                                          const uint64_t* __restrict__ offsets,
+                                                          uint64_t n_pixels,
+                                                          uint32_t* __restrict__ status,
+                                                          uint32_t* __restrict__ layer_start,
+                                                          uint32_t* __restrict__ mid_count) {
+  __shared__ uint32_t s_flags;
+  const uint32_t e = blockIdx.x;
+  if (threadIdx.x == 0) {
+    s_flags = 0;
+    if (e == 0) *mid_count = 0;
+  }
+  __syncthreads();
+  const uint64_t b = offsets[e], end = offsets[e + 1];
+  if (b <= end && end <= n_pixels)
+    validate_words(px + b, (uint32_t)(end - b), layer_start + 27ull * e, &s_flags);
+  __syncthreads();
+  if (threadIdx.x == 0) status[e] = s_flags;
 }
 
 // offsets of event e are usable (monotone and inside the buffer)
@@ -493,12 +501,9 @@ hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint3
   uint32_t* scratch = (uint32_t*)(base + up(4) + up(4ull * kLayers * n_events));
   uint64_t* scratch64 = (uint64_t*)((char*)scratch + up(5ull * 4 * n_pixels));
   HitsOut o{h->x, h->y, h->key, h->aux};
-  if (!validated) {
-    hipLaunchKernelGGL(k_clear, dim3((n_events + 255) / 256), dim3(256), 0, s, h->status, n_events,
-                       mid_count);
+  if (!validated)
     hipLaunchKernelGGL(k_validate, dim3(n_events), dim3(kValThreads), 0, s, px, offsets, n_pixels,
-                       h->status, h->layer_start);
-  }
+                       h->status, h->layer_start, mid_count);
   SmallArgs a{px, offsets, n_pixels, h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list};
   if (cfg.small_grid == 0)
     hipLaunchKernelGGL(k_small, dim3(n_events * kLayers), dim3(64), 0, s, a);

@@ -861,15 +861,18 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 // Azimuth tables of every (event, plane): one 64-lane workgroup per plane,
 // counting sort of the plane's hits by pseudo-angle bucket; at every bucket
 // position the hit's coordinates and local index.  The order inside a bucket
-// is irrelevant: every use scans whole buckets.
+// is irrelevant: every use scans whole buckets.  Workgroup 0 also clears the
+// lengths of the tiers' hand-over lists, which the tiers read after this kernel.
 __global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, const float* __restrict__ Y,
                                                    const uint32_t* __restrict__ hstatus,
                                                    const uint32_t* __restrict__ lstart,
                                                    const uint32_t* __restrict__ lnh,
                                                    const uint64_t* __restrict__ offsets,
-                                                   uint64_t n_pixels, AzOut az) {
+                                                   uint64_t n_pixels, AzOut az,
+                                                   uint32_t* __restrict__ esc_counts) {
   __shared__ uint32_t cnt[kNB];
   const uint32_t seg = blockIdx.x, e = seg / kLayers, l = seg % kLayers;
+  if (seg == 0 && threadIdx.x < 3) esc_counts[threadIdx.x] = 0;  // the tiers' hand-over lists
   const uint64_t b0 = offsets[e], b1 = offsets[e + 1];
   if (hstatus[e] != 0 || b1 < b0 || b1 > n_pixels) return;
   azimuth_tables<64>(X, Y, b0 + lstart[27ull * e + l], lnh[seg], seg, cnt, nullptr, az);
@@ -1040,6 +1043,7 @@ constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, k
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct FindWs {
+  uint32_t* esc_counts;  // [3] hand-over list lengths: small -> middle -> large -> workspace tier
   uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *esc3_count, *esc3_list, *order, *bst;
   float *xs, *ys;
   GlobalTabs g;
@@ -1051,11 +1055,12 @@ static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, Find
   auto take = [&](size_t bytes) { char* r = w ? w + o : nullptr; o += up256(bytes); return r; };
   const uint64_t nt = n_pixels / 3 + 1;
   FindWs f;
-  f.esc_count = (uint32_t*)take(4);
+  f.esc_counts = (uint32_t*)take(12);
+  f.esc_count = f.esc_counts;
+  f.esc2_count = f.esc_counts ? f.esc_counts + 1 : nullptr;
+  f.esc3_count = f.esc_counts ? f.esc_counts + 2 : nullptr;
   f.esc_list = (uint32_t*)take(4ull * n_events);
-  f.esc2_count = (uint32_t*)take(4);
   f.esc2_list = (uint32_t*)take(4ull * n_events);
-  f.esc3_count = (uint32_t*)take(4);
   f.esc3_list = (uint32_t*)take(4ull * n_events);
   f.order = (uint32_t*)take(4ull * n_pixels);
   f.xs = (float*)take(4ull * n_pixels);
@@ -1113,11 +1118,9 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   FindArgs a{f.xs, f.ys, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
              n_pixels, t->n_tracks, t->nhits, t->hit_idx, t->status, f.esc_count, f.esc_list};
   const FindConst c = make_find_const(p);
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc_count, 0u, f.esc_count);
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc2_count, 0u, f.esc2_count);
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, f.esc3_count, 0u, f.esc3_count);
   hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
-                     h->layer_start, h->layer_nhits, offsets, n_pixels, AzOut{f.order, f.xs, f.ys, f.bst});
+                     h->layer_start, h->layer_nhits, offsets, n_pixels, AzOut{f.order, f.xs, f.ys, f.bst},
+                     f.esc_counts);
   const bool ws_mode = cfg.small_grid != 0;
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
   const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
