@@ -9,14 +9,25 @@ namespace velo {
 
 constexpr uint32_t kNB = 256;  // azimuth buckets per plane
 
-// Monotone pseudo-angle of (x, y) in [0, 4]; its derivative with respect to
-// the azimuth is between 1/2 and 1, so an azimuth window of half width d is
-// contained in the pseudo-angle window of the same half width.
+// Upper bound of the pseudo-angle's derivative with respect to the azimuth:
+// an azimuth window of half width d lies inside the pseudo-angle window of
+// half width kPaSlope * d.
+constexpr float kPaSlope = 0.6502f;
+
+// Monotone pseudo-angle of (x, y) in [0, 4]: in every octant, with u the
+// ratio of the smaller to the larger of |x| and |y|, g(u) = 0.64 u /
+// (1 + 0.28 u^2) (a rational approximation of 2 atan(u) / pi, g(1) = 1/2).
+// Its derivative with respect to the azimuth lies in [0.5625, 0.6502] (2/pi is
+// 0.6366), so buckets of equal pseudo-angle width cover nearly equal azimuth
+// ranges and windows stay close to the exact azimuth windows.
 __device__ __forceinline__ float pangle(float x, float y) {
-  float ax = fabsf(x), ay = fabsf(y), d = ax + ay;
-  // hardware reciprocal (about 1 ulp): bucket assignment and window centres use
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+  // hardware reciprocals (about 1 ulp): bucket assignment and window centres use
   // this same function, and every window carries a margin far above its error
-  float r = d > 0.0f ? ay * __builtin_amdgcn_rcpf(d) : 0.0f;
+  const float u = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float g = (0.64f * u) * __builtin_amdgcn_rcpf(1.0f + (0.28f * u) * u);
+  const float r = ay <= ax ? g : 1.0f - g;  // from the x axis towards the y axis
   if (y >= 0.0f) return x >= 0.0f ? r : 2.0f - r;
   return x < 0.0f ? 2.0f + r : 4.0f - r;
 }

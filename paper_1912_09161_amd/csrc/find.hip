@@ -170,12 +170,13 @@ __device__ __forceinline__ Ranges window(float c, float d, uint32_t nb) {
 }
 
 // pseudo-angle half width for hits within rho of the point (x, y) at radius
-// R: the azimuth moves by at most asin(rho / R) <= rho / sqrt(R^2 - rho^2);
-// hardware reciprocal square root (about 1 ulp) under a 0.1 % + 1e-3 margin
+// R: the azimuth moves by at most asin(rho / R) <= rho / sqrt(R^2 - rho^2),
+// the pseudo-angle by at most kPaSlope times that; hardware reciprocal square
+// root (about 1 ulp) under a 0.1 % + 1e-3 margin
 __device__ __forceinline__ float point_window(float x, float y, float rho) {
   const float R2 = x * x + y * y, rho2 = rho * rho;
   if (R2 <= 2.25f * rho2) return 4.0f;  // R <= 1.5 rho: whole plane
-  return rho * __builtin_amdgcn_rsqf(R2 - rho2) * 1.001f + 1e-3f;
+  return (kPaSlope * rho) * __builtin_amdgcn_rsqf(R2 - rho2) * 1.001f + 1e-3f;
 }
 
 template <typename F>
@@ -589,6 +590,27 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         ty = (y1 - y0) / dz01;
         return fabsf(tx) <= P.max_t && fabsf(ty) <= P.max_t;
       };
+      // the slope cut |fl(d / dz01)| <= max_t without the division: the product
+      // with the rounded reciprocal is within 2^-23 (relative) of the quotient, so
+      // it decides every case outside a relative 1e-5 of the cut, and the
+      // division decides the rest
+      const float inv01 = 1.0f / dz01;
+      const float t_in = P.max_t * 0.99999f, t_out = P.max_t * 1.00001f;
+      auto slope_ok = [&](float d) {
+        const float q = fabsf(d * inv01);
+        if (q < t_in) return true;
+        if (q > t_out) return false;
+        return fabsf(d / dz01) <= P.max_t;
+      };
+      // the doublet cuts without the slopes' values (same decisions as doublet())
+      auto doublet_ok = [&](float x0, float y0, float x1, float y1) {
+        const float cr = x0 * y1 - y0 * x1;
+        const float r0s = x0 * x0 + y0 * y0;
+        const float r1s = x1 * x1 + y1 * y1;
+        if (!(cr * cr <= (P.sin2 * r0s) * r1s)) return false;
+        if (!(x0 * x1 + y0 * y1 > 0.0f)) return false;
+        return slope_ok(x1 - x0) && slope_ok(y1 - y0);
+      };
       if constexpr (RING) {
         // (a) window of every unused middle hit on plane l+2, prefix of the sizes
         uint32_t carry = 0;
@@ -644,8 +666,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 #pragma unroll
               for (uint32_t q = 0; q < 4; ++q) {
                 if (g + q >= stop || u0[q]) continue;
-                float tx, ty;
-                if (!doublet(x0[q], y0[q], x1, y1, tx, ty)) continue;
+                if (!doublet_ok(x0[q], y0[q], x1, y1)) continue;
                 const uint32_t d = atomicAdd(&sc.nd, 1u);
                 if (d < M.capD) M.dbl[d] = pj[q] | (i1 << 16);
               }
@@ -1096,7 +1117,9 @@ FindConst make_find_const(const velo_params* p) {
   c.s_fwd = p->s_fwd;
   c.max_skip = p->max_skip;
   const double u2 = p->sin2_phi;
-  c.win_doublet = (u2 >= 0.5 || u2 < 0) ? 4.0f : (float)(sqrt(u2 / (1.0 - u2)) * 1.001 + 1e-3);
+  // azimuth difference <= asin(sqrt(u2)) <= sqrt(u2 / (1 - u2)), times the pseudo-angle's slope
+  c.win_doublet = (u2 >= 0.5 || u2 < 0) ? 4.0f
+                                        : (float)(kPaSlope * sqrt(u2 / (1.0 - u2)) * 1.001 + 1e-3);
   c.rho_seed = (float)(sqrt((double)(p->s_seed > 0 ? p->s_seed : 0)) * 1.001 + 1e-6);
   c.rho_fwd = (float)(sqrt((double)(p->s_fwd > 0 ? p->s_fwd : 0)) * 1.001 + 1e-6);
   return c;
