@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
-constexpr uint32_t kSCapL = 352, kSCapT = 288, kSCapC = 384, kSCapD = 3 * kSCapT;
+constexpr uint32_t kSCapL = 352, kSCapT = 320, kSCapC = 384, kSCapD = 3 * kSCapT;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;
