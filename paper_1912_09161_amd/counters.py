@@ -50,7 +50,7 @@ def summarize(fetch_csv: str, write_csv: str, copy_mb: int) -> dict:
         n = defaultdict(int)
         for r in rows:
             name = _short(r["Kernel_Name"])
-            if not name.startswith("k_") and name != "k_clear":
+            if not name.startswith("k_"):
                 continue
             k[name] += float(r["Counter_Value"]) * 1024.0 * factor
             n[name] += 1
