@@ -24,11 +24,12 @@
 // slots, hit lists and counts are written directly; no atomics decide an
 // output position.
 //
-// Four tiers share one implementation: 256 lanes with small, middle and large
-// LDS tables, and 256 lanes reading the bucket tables in place with per-event
-// scratch in the caller's workspace at the event's own hit / track positions.
-// An event whose tables outgrow its tier is re-run from scratch by the next
-// tier.
+// Four tiers share one implementation: a 256-lane workgroup per event with
+// small LDS tables, persistent 512- and 1024-lane workgroups with middle and
+// large LDS tables, and 256 lanes reading the bucket tables in place with
+// per-event scratch in the caller's workspace at the event's own hit / track
+// positions.  An event whose tables outgrow its tier is re-run from scratch by
+// the next tier.
 #include "azimuth.hpp"
 
 namespace velo {
