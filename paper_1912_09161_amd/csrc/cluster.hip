@@ -263,7 +263,7 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
 // ---------------------------------------------------------------------------
 
 constexpr int kValThreads = 256;
-constexpr uint32_t kValUnroll = 4;  // words in flight per lane
+constexpr uint32_t kValUnroll = 8;  // words in flight per lane
 
 // Flags of the n words of one event (OR-ed into *flags, in LDS) and its plane
 // boundaries ls[0..26]; kValThreads lanes, kValUnroll words in flight per lane.

@@ -54,7 +54,7 @@ __device__ __forceinline__ void kf_transport(Kf1& s, float dz) {
   s.c01 = s.c01 + dz * s.c11;
 }
 
-constexpr int kFitThreads = 128;
+constexpr int kFitThreads = 256;
 
 struct FitOut {
   float x, y, z, tx, ty, cx[3], cy[3], chi2;
