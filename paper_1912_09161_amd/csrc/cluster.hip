@@ -24,7 +24,7 @@ namespace velo {
 constexpr uint32_t kSmallCap = 448;   // words per segment handled by one wave
 constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
 static_assert(kMidCap >= (uint32_t)kPix, "the workspace row table lives at the segment's own positions");
-constexpr int kMidThreads = 256;
+constexpr int kMidThreads = 512;
 static_assert(kSmallCap % 64 == 0 && kMidCap % kMidThreads == 0, "register staging of the words");
 constexpr uint32_t kDupBit = 0x80000000u;
 
