@@ -12,7 +12,7 @@
 //               then rank inside the row), 8-neighbour union-find (roots =
 //               smallest addresses), integer charge sums, ordered emission by
 //               a prefix count; larger segments are appended to a work list
-//   k_mid       persistent 256-lane workgroups over the work list: the same
+//   k_mid       persistent 512-lane workgroups over the work list: the same
 //               algorithm in LDS up to kMidCap words, else in the caller's
 //               workspace at the segment's own word positions
 //   k_finalize  one thread per event: per-event status, hit counts, zeroed
@@ -22,7 +22,7 @@
 namespace velo {
 
 constexpr uint32_t kSmallCap = 448;   // words per segment handled by one wave
-constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by 256 lanes
+constexpr uint32_t kMidCap = 2048;    // words per segment handled in LDS by one workgroup
 static_assert(kMidCap >= (uint32_t)kPix, "the workspace row table lives at the segment's own positions");
 constexpr int kMidThreads = 512;
 static_assert(kSmallCap % 64 == 0 && kMidCap % kMidThreads == 0, "register staging of the words");
