@@ -191,12 +191,14 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
   OrderWs ow;
   order_ws_layout((char*)c.ws + main_ws, c.n_events, &ow);
   if (stages & 1) {
-    // clearing, validation, size ordering, clustering
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
+    // clearing (only the persistent kernels and the size orders use the
+    // counters), validation, size ordering, clustering
+    const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
+    if (mode)
+      hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
     hipLaunchKernelGGL(k_validate, dim3(c.n_events), dim3(kValThreads), 0, s, c.px, c.offsets,
                        c.n_pixels, c.hits.status, c.hits.layer_start, (uint32_t*)c.ws);
     // size orders for the persistent kernels that use them
-    const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
     if (mode) {
       const uint32_t og = (order_items(c.n_events, mode) + kOrderThreads - 1) / kOrderThreads;
       hipLaunchKernelGGL(k_order_hist, dim3(og), dim3(kOrderThreads), 0, s, c.offsets, c.hits.status,
@@ -210,7 +212,8 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
     if (e != hipSuccess) return e;
   }
   if (stages & 2) {
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 3u);
+    if (k.find_grid)  // work-stealing counters of the persistent track-finding tiers
+      hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 3u);
     const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2};
     hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
                                    c.ws, s, fc);
