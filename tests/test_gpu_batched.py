@@ -96,3 +96,41 @@ def test_batched_inside_a_caller_graph():
         _ = (px.to(torch.int64).sum() + r).item()
         same(host(bufs), ref, b)
     ctx.close()
+
+
+def test_batched_with_classifier_equals_plain_mlp():
+    """The batched form with the classifier fused after the fit equals the plain
+    reconstruction with the same classifier: hits, tracks, states, scores and
+    decisions bit for bit (first call tuned and captured, then a replay)."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    from gpu_helpers import track_slots
+    from paper_1912_09161_amd import learn
+    b = generate("uneven", 600, workers=8)
+    P = velo.default_params()
+    px, off = to_dev(b.pixels, b.offsets)
+    p = learn.he_uniform(9)
+    p[256:288] = np.random.default_rng(3).normal(0, 0.2, 32)
+    p[1312:1344] = np.random.default_rng(4).normal(0, 0.2, 32)
+    mean = torch.tensor([3.0, 10.0, 0.5, 0.0, 0.0, 3.5, 300.0, -100.0], device="cuda")
+    std = torch.tensor([2.0, 4.0, 1.0, 0.1, 0.1, 0.8, 300.0, 300.0], device="cuda")
+    probe = host(velo.reconstruct_mlp(px, off, velo.Mlp(torch.from_numpy(p).cuda(), mean, std, 0.0), params=P))
+    sl = track_slots(probe["tracks"], b.offsets)
+    mlp = velo.Mlp(torch.from_numpy(p).cuda(), mean, std, float(np.median(probe["states"]["score"][sl])))
+    ref = velo.reconstruct_mlp(px, off, mlp, params=P)
+    torch.cuda.synchronize()
+    ref = host(ref)
+    ctx = velo.Context()
+    stream = torch.cuda.Stream()
+    bufs = None
+    for r in range(2):
+        with torch.cuda.stream(stream):
+            bufs = ctx.reconstruct(px, off, params=P, mlp=mlp, bufs=bufs, stream=stream)
+        stream.synchronize()
+        g = host(bufs)
+        same(g, ref, b)
+        for k in ("score", "accepted"):
+            np.testing.assert_array_equal(g["states"][k][sl].view(np.uint8), ref["states"][k][sl].view(np.uint8))
+        assert 0 < ref["states"]["accepted"][sl].sum() < len(sl)
+    ctx.close()
