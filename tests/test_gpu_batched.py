@@ -134,3 +134,35 @@ def test_batched_with_classifier_equals_plain_mlp():
             np.testing.assert_array_equal(g["states"][k][sl].view(np.uint8), ref["states"][k][sl].view(np.uint8))
         assert 0 < ref["states"]["accepted"][sl].sum() < len(sl)
     ctx.close()
+
+
+def test_batched_edge_events():
+    """Empty events, flagged events (bad words, hole pixels, plane order,
+    duplicates) and an event with one huge cluster through the batched form:
+    statuses, hits, tracks and states equal the plain form's."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    from synth.raw import line_event, pack, word
+    good = line_event([(0.02 * 600, 0.015 * 600, 0.02, 0.015), (-0.01 * 600, 0.02 * 600, -0.01, 0.02)])
+    blob = [word(9, 400 + r, 400 + c, 1 + (r * 7 + c) % 15) for r in range(40) for c in range(40)]
+    events = [[], good, good + [word(2, 20, 20, 3)], [word(0, 10, 10, 0)], [word(0, 768, 768, 3)],
+              [word(4, 100, 100, 3), word(4, 100, 100, 5)], [word(4, 100, 100, 3), word(3, 100, 100, 5)],
+              sorted(good + blob, key=lambda w: (w >> 22) & 31), [], good]
+    px_h, off_h = pack(events)
+    b = type("B", (), {"offsets": off_h})()
+    P = velo.default_params()
+    ref = plain(type("B", (), {"pixels": px_h, "offsets": off_h})(), P)
+    px, off = to_dev(px_h, off_h)
+    ctx = velo.Context()
+    stream = torch.cuda.Stream()
+    bufs = None
+    for r in range(2):
+        with torch.cuda.stream(stream):
+            bufs = ctx.reconstruct(px, off, params=P, bufs=bufs, stream=stream)
+        stream.synchronize()
+        g = host(bufs)
+        np.testing.assert_array_equal(g["hits"]["status"], ref["hits"]["status"])
+        same(g, ref, b)
+    assert ref["hits"]["status"].any() and ref["tracks"]["n_tracks"][-1] >= 1
+    ctx.close()
