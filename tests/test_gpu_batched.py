@@ -166,3 +166,27 @@ def test_batched_edge_events():
         same(g, ref, b)
     assert ref["hits"]["status"].any() and ref["tracks"]["n_tracks"][-1] >= 1
     ctx.close()
+
+
+def test_batched_graph_cache_alternating_batches():
+    """One context, two batches of different sizes in different buffers, called
+    alternately: every call replays the graph of its own buffers and equals the
+    plain form (a replay of the wrong graph would write the other batch)."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    P = velo.default_params()
+    bs = [generate("nominal", 150, workers=8), generate("uneven", 220, first_event=500, workers=8)]
+    refs = [plain(b, P) for b in bs]
+    devs = [to_dev(b.pixels, b.offsets) for b in bs]
+    ctx = velo.Context()
+    stream = torch.cuda.Stream()
+    bufs = [None, None]
+    for r in range(5):
+        k = r % 2
+        px, off = devs[k]
+        with torch.cuda.stream(stream):
+            bufs[k] = ctx.reconstruct(px, off, params=P, bufs=bufs[k], stream=stream)
+        stream.synchronize()
+        same(host(bufs[k]), refs[k], bs[k])
+    ctx.close()
