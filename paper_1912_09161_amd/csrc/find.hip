@@ -1057,7 +1057,7 @@ constexpr uint32_t kSCapL = 352, kSCapT = 320, kSCapC = 384, kSCapD = 3 * kSCapT
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;
-constexpr uint32_t kMCapL = 640, kMCapT = 512, kMCapC = 1024, kMCapD = 2048, kMBlocks = 512;
+constexpr uint32_t kMCapL = 640, kMCapT = 512, kMCapC = 1024, kMCapD = 2304, kMBlocks = 512;
 static_assert(kMCapL <= (1u << kPosBits) && kMCapT <= (1u << kPosBits), "packed positions");
 constexpr int kLThreads = 1024;
 constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, kLBlocks = 256;
