@@ -178,3 +178,19 @@ def test_small_tier_capacity_edges(orc):
     per_plane = o["hits"]["layer_nhits"].reshape(-1, 26).max(1)
     assert per_plane[0] == 352 and per_plane[1] == 353 and per_plane[2] == 340
     assert o["tracks"]["n_tracks"][2] > 600
+
+
+def test_larger_tier_capacity_edges(orc):
+    """One plane at the middle tier's limit (640 hits) and one above it (641,
+    to the large tier), at the large tier's limit (1024) and above it (1025, to
+    the workspace tier, which then completes normally): every event equals the
+    oracle."""
+    def grid_plane(l, n):  # n isolated pixels on plane l
+        return [word(l, 100 + 2 * (k // 600), 100 + 2 * (k % 600), 3) for k in range(n)]
+
+    good = line_event([(0.02 * 600, 0.015 * 600, 0.02, 0.015)])
+    events = [sorted(good + grid_plane(20, n - 1), key=lambda w: (w >> 22) & 31) for n in (640, 641, 1024, 1025)]
+    px, off = pack(events)
+    g, o, _ = run_pair(orc, px, off)
+    assert list(o["hits"]["layer_nhits"].reshape(-1, 26).max(1)) == [640, 641, 1024, 1025]
+    assert list(g["tracks"]["n_tracks"]) == [1, 1, 1, 1] and not g["tracks"]["status"].any()
