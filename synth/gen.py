@@ -363,8 +363,9 @@ def _chunk_part(args):
 def generate(cfg, n_events: int | None = None, first_event: int = 0, workers: int = 1) -> EventBatch:
     """Events [first_event, first_event + n_events) of a config (name or Config).
 
-    workers > 1 draws the chunks in a process pool (the result is identical);
-    call it before the process initialises a GPU, since the pool forks."""
+    workers > 1 draws the chunks on a thread pool (the result is identical;
+    numpy releases the interpreter lock in the bulk work).  No process is
+    forked, so it may be called at any time, also after a GPU is in use."""
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
     if n_events is None:
@@ -376,9 +377,9 @@ def generate(cfg, n_events: int | None = None, first_event: int = 0, workers: in
     jobs = [(cfg, ch, max(first_event - ch * CHUNK, 0), min(first_event + n_events - ch * CHUNK, CHUNK))
             for ch in range(c0, c1 + 1)]
     if workers > 1 and len(jobs) > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-            parts = pool.map(_chunk_part, jobs)
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(workers, len(jobs))) as pool:
+            parts = list(pool.map(_chunk_part, jobs))
     else:
         parts = [_chunk_part(j) for j in jobs]
     return parts[0] if len(parts) == 1 else concat(parts)

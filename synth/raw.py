@@ -61,3 +61,35 @@ def shuffle_within_layers(pixels: np.ndarray, offsets: np.ndarray, seed: int) ->
         k = rng.random(len(w))
         out[a:b] = w[np.lexsort((k, lay))]
     return out
+
+
+def hit_event(planes: dict, n_slots: int | None = None) -> tuple[dict, np.ndarray]:
+    """One event of hand-placed hits in the hit layout that clustering writes,
+    for feeding track finding directly.
+
+    planes: {plane: [(x_mm, y_mm, id), ...]}; a hit's key is plane << 22 | id
+    (ids unique inside a plane).  Hits of a plane are stored by ascending key.
+    n_slots (default: the number of hits) sets offsets[1], the event's slot
+    range, which also fixes its track capacity floor(n_slots / 3).
+    Returns (hits, offsets) with hits = dict(x, y, key, aux, layer_start[1, 27],
+    layer_nhits[1, 26], n_hits[1], status[1])."""
+    rows = []
+    for l in sorted(planes):
+        for x, y, i in sorted(planes[l], key=lambda h: h[2]):
+            rows.append((l, np.float32(x), np.float32(y), (int(l) << 22) | int(i)))
+    n = len(rows)
+    N = max(n if n_slots is None else int(n_slots), n, 1)
+    x = np.zeros(N, np.float32)
+    y = np.zeros(N, np.float32)
+    key = np.zeros(N, np.uint32)
+    for k, (l, xv, yv, kv) in enumerate(rows):
+        x[k], y[k], key[k] = xv, yv, kv
+    nh = np.zeros((1, 26), np.uint32)
+    for l, *_ in rows:
+        nh[0, l] += 1
+    ls = np.zeros((1, 27), np.uint32)
+    ls[0, 1:] = np.cumsum(nh[0])
+    ls[0, 26] = N
+    hits = dict(x=x, y=y, key=key, aux=np.full(N, (1 << 16) | 1, np.uint32), layer_start=ls,
+                layer_nhits=nh, n_hits=np.array([n], np.uint32), status=np.zeros(1, np.uint32))
+    return hits, np.array([0, N], np.uint64)

@@ -212,12 +212,8 @@ def efficiency_ghosts(particle_uid, accepted, reco_uid) -> dict:
                 clone_rate=(n_m - len(pairs)) / max(n_m, 1))
 
 
-_JOB = None
-
-
-def _label_chunk(rng):
-    e0, e1, t0, t1 = rng
-    b, ev, nh, keys = _JOB
+def _label_chunk(job):
+    b, ev, nh, keys, (e0, e1, t0, t1) = job
     T = Truth(b.range(e0, e1))
     m = match_tracks(T, ev[t0:t1] - e0, nh[t0:t1], keys[t0:t1])
     reco = ((T.reco_ev[T.reco_ok] + e0) << 35) | T.reco_pid[T.reco_ok]
@@ -225,10 +221,9 @@ def _label_chunk(rng):
 
 
 def track_labels_parallel(batch, tracks: dict, hits: dict, workers: int = 8, chunk: int = 250):
-    """track_labels(Truth(batch), ...) computed over chunks of events in worker
-    processes (fork start method; the batch is shared copy-on-write)."""
-    import multiprocessing as mp
-    global _JOB
+    """track_labels(Truth(batch), ...) computed over chunks of events on a
+    thread pool (no process is forked)."""
+    from concurrent.futures import ThreadPoolExecutor
     ev, slot, nh, keys = track_list(tracks, hits, batch.offsets)
     E = batch.n_events
     if workers <= 1 or E <= chunk:
@@ -237,14 +232,10 @@ def track_labels_parallel(batch, tracks: dict, hits: dict, workers: int = 8, chu
         reco = (T.reco_ev[T.reco_ok] << 35) | T.reco_pid[T.reco_ok]
     else:
         bounds = np.searchsorted(ev, np.arange(0, E + chunk, chunk).clip(max=E))
-        jobs = [(e0, min(e0 + chunk, E), int(bounds[i]), int(bounds[i + 1]))
+        jobs = [(batch, ev, nh, keys, (e0, min(e0 + chunk, E), int(bounds[i]), int(bounds[i + 1])))
                 for i, e0 in enumerate(range(0, E, chunk))]
-        _JOB = (batch, ev, nh, keys)
-        try:
-            with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-                res = pool.map(_label_chunk, jobs)
-        finally:
-            _JOB = None
+        with ThreadPoolExecutor(min(workers, len(jobs))) as pool:
+            res = list(pool.map(_label_chunk, jobs))
         m = np.concatenate([r[0] for r in res]) if res else np.zeros(0, np.int64)
         reco = np.concatenate([r[1] for r in res]) if res else np.zeros(0, np.int64)
     uid = np.where(m >= 0, (np.asarray(ev, np.int64) << 35) | np.maximum(m, 0), -1)
