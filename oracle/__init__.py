@@ -7,16 +7,21 @@ shares no code with the HIP implementation.
 """
 from .oracle import (  # noqa: F401
     DEFAULT_PARAMS,
+    EV_BAD_OFFSETS,
     EV_BAD_WORD,
     EV_DUPLICATE,
     EV_HOLE,
     EV_LAYER_ORDER,
     EV_OVERFLOW,
+    EV_PV_OVERFLOW,
+    MAX_PVS,
+    PvParams,
     MAX_CANDIDATES,
     N_PARAMS,
     build,
     cluster,
     features,
+    find_pvs,
     find_tracks,
     fit,
     fit_points,
@@ -25,5 +30,6 @@ from .oracle import (  # noqa: F401
     mlp_forward,
     mlp_forward_bf16,
     mlp_fwd_bwd,
+    pv_params,
     reconstruct,
 )

@@ -12,7 +12,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "velo_oracle.c"), os.path.join(_HERE, "velo_oracle_mlp.c")]
+_SRCS = [os.path.join(_HERE, f) for f in ("velo_oracle.c", "velo_oracle_mlp.c", "velo_oracle_pv.c")]
 _LIB = os.path.join(_HERE, "libvelo_oracle.so")
 
 EV_BAD_WORD = 1
@@ -20,7 +20,10 @@ EV_LAYER_ORDER = 2
 EV_DUPLICATE = 4
 EV_HOLE = 8
 EV_OVERFLOW = 16
+EV_BAD_OFFSETS = 32
+EV_PV_OVERFLOW = 64
 MAX_CANDIDATES = 65536
+MAX_PVS = 64
 
 # Default cut and filter constants (a reading of the paper, which gives only
 # the 400 MeV transverse momentum of the scattering model).
@@ -62,7 +65,7 @@ def _L():
         lib = C.CDLL(_LIB)
         P = C.c_void_p
         lib.velo_oracle_cluster.restype = C.c_uint32
-        lib.velo_oracle_cluster.argtypes = [P, P, C.c_uint32] + [P] * 8
+        lib.velo_oracle_cluster.argtypes = [P, P, C.c_uint32, C.c_uint32, C.c_uint64] + [P] * 8
         lib.velo_oracle_find_tracks.restype = None
         lib.velo_oracle_find_tracks.argtypes = [P, P, P, P, P, P, C.c_uint32, P, P, P, P, P]
         lib.velo_oracle_fit.restype = None
@@ -78,6 +81,10 @@ def _L():
         lib.velo_oracle_mlp_fwd_bwd.argtypes = [P, P, P, C.c_int64, P]
         lib.velo_oracle_mlp_forward.restype = None
         lib.velo_oracle_mlp_forward.argtypes = [P, P, C.c_int64, P]
+        lib.velo_oracle_pv_params_default.restype = None
+        lib.velo_oracle_pv_params_default.argtypes = [P]
+        lib.velo_oracle_find_pvs.restype = None
+        lib.velo_oracle_find_pvs.argtypes = [P, C.c_uint32] + [P] * 13
         lib.velo_oracle_mlp_forward_bf16.restype = None
         lib.velo_oracle_mlp_forward_bf16.argtypes = [P, P, P, P, C.c_int64, P]
         _lib = lib
@@ -100,12 +107,13 @@ def layer_z(l: int) -> float:
 
 
 def cluster(pixels, offsets, events=None) -> dict:
-    """Cluster all events (or the half-open event range `events`)."""
+    """Cluster all events (or the half-open event range `events`); the batch
+    holds len(pixels) words."""
     pixels = np.ascontiguousarray(pixels, np.uint32)
     offsets = np.ascontiguousarray(offsets, np.uint64)
     E = len(offsets) - 1
     e0, e1 = (0, E) if events is None else events
-    N = max(int(offsets[-1]), 1)
+    N = max(len(pixels), 1)
     out = dict(x=np.zeros(N, np.float32), y=np.zeros(N, np.float32),
                key=np.zeros(N, np.uint32), aux=np.zeros(N, np.uint32),
                layer_start=np.zeros((E, 27), np.uint32), layer_nhits=np.zeros((E, 26), np.uint32),
@@ -117,17 +125,17 @@ def cluster(pixels, offsets, events=None) -> dict:
 def cluster_into(pixels, offsets, e0, e1, out):
     if e1 <= e0:
         return
-    _L().velo_oracle_cluster(_p(pixels), _p(offsets, e0), e1 - e0,
+    _L().velo_oracle_cluster(_p(pixels), _p(offsets), e0, e1, len(pixels),
                              _p(out["x"]), _p(out["y"]), _p(out["key"]), _p(out["aux"]),
-                             _p(out["layer_start"], 27 * e0), _p(out["layer_nhits"], 26 * e0),
-                             _p(out["n_hits"], e0), _p(out["status"], e0))
+                             _p(out["layer_start"]), _p(out["layer_nhits"]),
+                             _p(out["n_hits"]), _p(out["status"]))
 
 
 def find_tracks(hits: dict, offsets, params=None, events=None) -> dict:
     offsets = np.ascontiguousarray(offsets, np.uint64)
     E = len(offsets) - 1
     e0, e1 = (0, E) if events is None else events
-    cap = max(int(offsets[-1]) // 3, 1)
+    cap = max(len(hits["x"]) // 3, 1)
     out = dict(n_tracks=np.zeros(E, np.uint32), nhits=np.zeros(cap, np.uint8),
                hit_idx=np.zeros((cap, 26), np.uint32), status=np.zeros(E, np.uint32))
     find_into(hits, offsets, e0, e1, _params(params), out)
@@ -148,7 +156,7 @@ def fit(hits: dict, tracks: dict, offsets, params=None, events=None) -> dict:
     offsets = np.ascontiguousarray(offsets, np.uint64)
     E = len(offsets) - 1
     e0, e1 = (0, E) if events is None else events
-    cap = max(int(offsets[-1]) // 3, 1)
+    cap = max(len(hits["x"]) // 3, 1)
     f = lambda: np.zeros(cap, np.float32)  # noqa: E731
     out = dict(x=f(), y=f(), z=f(), tx=f(), ty=f(), cov_x=np.zeros((cap, 3), np.float32),
                cov_y=np.zeros((cap, 3), np.float32), chi2=f(), ndof=np.zeros(cap, np.int32),
@@ -185,13 +193,14 @@ def fit_points(hx, hy, hz, hlayer, params=None):
 
 
 def reconstruct(pixels, offsets, params=None, events=None, threads: int = 1) -> dict:
-    """cluster -> find -> fit on a thread pool over contiguous event ranges."""
+    """cluster -> find -> fit on a thread pool over contiguous event ranges
+    (the batch holds len(pixels) words)."""
     pixels = np.ascontiguousarray(pixels, np.uint32)
     offsets = np.ascontiguousarray(offsets, np.uint64)
     E = len(offsets) - 1
     e0, e1 = (0, E) if events is None else events
-    N = max(int(offsets[-1]), 1)
-    cap = max(int(offsets[-1]) // 3, 1)
+    N = max(len(pixels), 1)
+    cap = max(len(pixels) // 3, 1)
     P = _params(params)
     hits = dict(x=np.zeros(N, np.float32), y=np.zeros(N, np.float32),
                 key=np.zeros(N, np.uint32), aux=np.zeros(N, np.uint32),
@@ -273,3 +282,39 @@ def mlp_forward_bf16(params, mean, std, f):
     z = np.zeros(len(f), np.float32)
     _L().velo_oracle_mlp_forward_bf16(_p(p), _p(m), _p(s), _p(f), len(f), _p(z))
     return z
+
+
+# ---------------------------------------------------------------------------
+# primary vertices
+
+
+class PvParams(C.Structure):
+    _fields_ = [("z0", C.c_float), ("bin_w", C.c_float), ("n_bins", C.c_int32), ("max_var", C.c_float),
+                ("seed_min", C.c_int32), ("nms", C.c_int32), ("chi2_cut", C.c_float),
+                ("n_iter", C.c_int32), ("min_weight", C.c_float)]
+
+
+def pv_params(**overrides) -> PvParams:
+    p = PvParams()
+    _L().velo_oracle_pv_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def find_pvs(states: dict, tracks: dict, offsets, params: PvParams | None = None) -> dict:
+    """PVs of every event from fitted states (velo_oracle_find_pvs)."""
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    P = params if params is not None else pv_params()
+    f32 = lambda k: np.ascontiguousarray(states[k], np.float32).ravel()  # noqa: E731
+    nt = np.ascontiguousarray(tracks["n_tracks"], np.uint32)
+    acc = np.ascontiguousarray(states["accepted"], np.uint8)
+    out = dict(n_pv=np.zeros(E, np.uint32), z=np.zeros((E, MAX_PVS), np.float32),
+               var=np.zeros((E, MAX_PVS), np.float32), weight=np.zeros((E, MAX_PVS), np.float32),
+               status=np.zeros(E, np.uint32))
+    z, tx, ty, cx, cy = f32("z"), f32("tx"), f32("ty"), f32("cov_x"), f32("cov_y")
+    _L().velo_oracle_find_pvs(_p(offsets), E, _p(nt), _p(z), _p(tx), _p(ty), _p(cx), _p(cy), _p(acc),
+                              C.byref(P), _p(out["n_pv"]), _p(out["z"]), _p(out["var"]),
+                              _p(out["weight"]), _p(out["status"]))
+    return out

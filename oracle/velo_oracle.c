@@ -139,18 +139,35 @@ static uint32_t cluster_event(const uint32_t* w, uint32_t n, uint64_t base,
     return 0;
 }
 
-uint32_t velo_oracle_cluster(const uint32_t* pixels, const uint64_t* offsets, uint32_t n_events,
+/* Usable offsets (reading of the per-event error convention): event e owns
+   words [offsets[e], offsets[e+1]) only if offsets[e] <= offsets[e+1] <=
+   n_pixels and no earlier offset exceeds offsets[e]; the word ranges of
+   usable events are then disjoint.  Any other event is flagged
+   VO_EV_BAD_OFFSETS and has no hits. */
+uint32_t velo_oracle_cluster(const uint32_t* pixels, const uint64_t* offsets, uint32_t e0,
+                             uint32_t e1, uint64_t n_pixels,
                              float* x, float* y, uint32_t* key, uint32_t* aux,
                              uint32_t* layer_start, uint32_t* layer_nhits,
                              uint32_t* n_hits, uint32_t* status)
 {
     uint32_t all = 0;
-    for (uint32_t e = 0; e < n_events; ++e) {
-        uint64_t b = offsets[e];
-        uint32_t n = (uint32_t)(offsets[e + 1] - b);
-        status[e] = cluster_event(pixels + b, n, b, x, y, key, aux,
-                                  layer_start + 27 * (size_t)e, layer_nhits + 26 * (size_t)e,
-                                  n_hits + e);
+    uint64_t before = 0;   /* largest of offsets[0 .. e-1] */
+    for (uint32_t e = 0; e < e0; ++e)
+        if (offsets[e] > before) before = offsets[e];
+    for (uint32_t e = e0; e < e1; ++e) {
+        uint64_t b = offsets[e], end = offsets[e + 1];
+        int usable = b <= end && end <= n_pixels && b >= before;
+        if (b > before) before = b;
+        if (!usable) {
+            status[e] = VO_EV_BAD_OFFSETS;
+            memset(layer_start + 27 * (size_t)e, 0, 27 * sizeof(uint32_t));
+            memset(layer_nhits + 26 * (size_t)e, 0, 26 * sizeof(uint32_t));
+            n_hits[e] = 0;
+        } else {
+            status[e] = cluster_event(pixels + b, (uint32_t)(end - b), b, x, y, key, aux,
+                                      layer_start + 27 * (size_t)e, layer_nhits + 26 * (size_t)e,
+                                      n_hits + e);
+        }
         all |= status[e];
     }
     return all;

@@ -18,6 +18,10 @@
  *                            scattering noise, then extrapolation to the
  *                            point of closest approach to the beamline
  *                            (Sec. 2.3.1, third and fourth paragraphs)
+ *   velo_oracle_find_pvs     primary vertices from a histogram of the
+ *                            tracks' beamline z and a weighted fit of every
+ *                            candidate with every track (Sec. 2.3.1, last
+ *                            paragraph)
  *
  * Every rule the paper leaves open (raw format, connectivity, cuts, tie
  * breaks, filter initialisation) is a written reading of the paper, stated
@@ -45,6 +49,11 @@ extern "C" {
 #define VO_EV_DUPLICATE    4u  /* two words with the same address (only reported when no other bit is set) */
 #define VO_EV_HOLE         8u  /* an otherwise valid word addresses an inactive (beam-hole) pixel */
 #define VO_EV_OVERFLOW    16u  /* a track-finding step exceeded VO_MAX_CANDIDATES candidates */
+#define VO_EV_BAD_OFFSETS 32u  /* offsets[e] > offsets[e+1], offsets[e+1] > n_pixels, or an
+                                  earlier offset above offsets[e] (the event's words may
+                                  overlap another event's) */
+
+#define VO_EV_PV_OVERFLOW 64u  /* more than VO_MAX_PVS vertex candidates (the first are kept) */
 
 /* Upper bound on the candidates (seed triplets, or track-hit pairs) of one
    track-finding step.  An event exceeding it is flagged and gets no tracks. */
@@ -62,18 +71,21 @@ typedef struct {
     float qc3, qc4;     /* chi2/ndof limits of 3-hit / >=4-hit tracks */
 } vo_params;
 
-/* Clustering of events [0, n_events).
-   pixels        raw words, absolute positions
-   offsets[n+1]  absolute word offsets (uint64)
+/* Clustering of events [e0, e1) of a batch.
+   pixels        raw words, absolute positions; n_pixels words
+   offsets[E+1]  absolute word offsets (uint64) of the whole batch (the
+                 offsets rule looks at every offset before the event)
    out hits      x, y, key, aux at absolute slot offsets[e] + layer_start[e][l] + rank
-   layer_start   [n*27] event-relative first slot of each layer (= index of the
+   layer_start   [E*27] event-relative first slot of each layer (= index of the
                  layer's first word in the event); [26] = words in the event
-   layer_nhits   [n*26] clusters per layer
-   n_hits        [n]    clusters per event
-   status        [n]    VO_EV_* bits; an event with any bit set has no hits and
+   layer_nhits   [E*26] clusters per layer
+   n_hits        [E]    clusters per event
+   status        [E]    VO_EV_* bits; an event with any bit set has no hits and
                         all its layer_start / layer_nhits entries are 0
-   returns the OR of all statuses */
-uint32_t velo_oracle_cluster(const uint32_t* pixels, const uint64_t* offsets, uint32_t n_events,
+   (per-event arrays indexed by the absolute event number)
+   returns the OR of the statuses of events [e0, e1) */
+uint32_t velo_oracle_cluster(const uint32_t* pixels, const uint64_t* offsets, uint32_t e0,
+                             uint32_t e1, uint64_t n_pixels,
                              float* x, float* y, uint32_t* key, uint32_t* aux,
                              uint32_t* layer_start, uint32_t* layer_nhits,
                              uint32_t* n_hits, uint32_t* status);
@@ -108,6 +120,34 @@ int32_t velo_oracle_fit_points(const float* hx, const float* hy, const float* hz
 
 /* float z of layer l */
 float velo_oracle_layer_z(int32_t l);
+
+/* Primary-vertex finding (velo_oracle_pv.c; Sec. 2.3.1, last paragraph):
+   histogram of the tracks' beamline z, peaks as vertex candidates, every
+   candidate fitted with every track under shared Tukey weights.  The
+   readings are listed at the top of velo_oracle_pv.c. */
+#define VO_MAX_PVS 64
+#define VO_MAX_PV_TRACKS 2048
+typedef struct {
+    float z0;          /* mm, lower edge of the histogram */
+    float bin_w;       /* mm, bin width */
+    int32_t n_bins;
+    float max_var;     /* mm^2, largest beamline-z variance of an admitted track */
+    int32_t seed_min;  /* smallest histogram count of a candidate bin */
+    int32_t nms;       /* bins on each side a candidate must dominate */
+    float chi2_cut;    /* Tukey cut */
+    int32_t n_iter;    /* fit rounds */
+    float min_weight;  /* smallest weight sum of a PV */
+} vo_pv_params;
+void velo_oracle_pv_params_default(vo_pv_params* p);
+/* PVs of events [0, n_events) from the fitted states of their tracks (track
+   slots floor(offsets[e]/3) + t, t < n_tracks[e], clamped to the event's
+   slots): n_pv[e]; pv_z, pv_var (variance of z), pv_w (weight sum) at
+   e * VO_MAX_PVS + k (zero beyond n_pv); pv_status[e] 0 or VO_EV_PV_OVERFLOW. */
+void velo_oracle_find_pvs(const uint64_t* offsets, uint32_t n_events, const uint32_t* n_tracks,
+                          const float* sz, const float* stx, const float* sty,
+                          const float* cov_x, const float* cov_y, const uint8_t* accepted,
+                          const vo_pv_params* P, uint32_t* n_pv, float* pv_z, float* pv_var,
+                          float* pv_w, uint32_t* pv_status);
 
 /* Learned track-quality classifier (velo_oracle_mlp.c): 8 features,
    8-32-32-1 network, 1377 parameters W1[32][8], b1[32], W2[32][32], b2[32],

@@ -93,3 +93,27 @@ def hit_event(planes: dict, n_slots: int | None = None) -> tuple[dict, np.ndarra
     hits = dict(x=x, y=y, key=key, aux=np.full(N, (1 << 16) | 1, np.uint32), layer_start=ls,
                 layer_nhits=nh, n_hits=np.array([n], np.uint32), status=np.zeros(1, np.uint32))
     return hits, np.array([0, N], np.uint64)
+
+
+def bad_offsets_case():
+    """Three generated events A, B, C packed back to back, and offset tables,
+    each with the status every event must get (32 = bad offsets): a
+    decreasing pair, a start below an earlier offset (the words would overlap
+    A's), an end beyond the buffer, a repeated offset (an empty event)."""
+    from .gen import generate
+    b = generate("cpu10", 3)
+    nA, nB, nC = (int(b.offsets[e + 1] - b.offsets[e]) for e in range(3))
+    N = nA + nB + nC
+    cases = {
+        # A | B | C, all fine
+        "good": ([0, nA, nA + nB, N], [0, 0, 0]),
+        # A, then a decreasing pair, then an event inside A's words, then the rest
+        "descent": ([0, nA, 40, 50, N], [0, 32, 32, 32]),
+        # A twice (the second start lies below the first event's end), C
+        "overlap": ([0, nA, 10, nA + nB, N], [0, 32, 32, 0]),
+        # A, B, then an end beyond the buffer
+        "beyond": ([0, nA, nA + nB, N + 5], [0, 0, 32]),
+        # an empty event at a repeated offset is fine
+        "empty": ([0, nA, nA, nA + nB, N], [0, 0, 0, 0]),
+    }
+    return b, cases

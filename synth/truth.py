@@ -240,3 +240,58 @@ def track_labels_parallel(batch, tracks: dict, hits: dict, workers: int = 8, chu
         reco = np.concatenate([r[1] for r in res]) if res else np.zeros(0, np.int64)
     uid = np.where(m >= 0, (np.asarray(ev, np.int64) << 35) | np.maximum(m, 0), -1)
     return slot, (m >= 0).astype(np.float32), uid, reco
+
+
+def pv_truth_tracks(batch, truth: Truth | None = None) -> np.ndarray:
+    """Number of reconstructible particles of every simulated PV (flat over
+    the batch's PVs, in batch.pv order)."""
+    truth = truth if truth is not None else Truth(batch)
+    n_pv = len(batch.pv["z"])
+    part_pv = batch.part["pv"].astype(np.int64)
+    part_ev = np.repeat(np.arange(batch.n_events), np.diff(batch.part_off.astype(np.int64)))
+    pv_first = batch.pv_off[:-1].astype(np.int64)
+    ok = truth.reco_ok
+    ev, pid = truth.reco_ev[ok], truth.reco_pid[ok]
+    part_first = batch.part_off[:-1].astype(np.int64)
+    gpart = part_first[ev] + pid
+    gpv = pv_first[part_ev[gpart]] + part_pv[gpart]
+    return np.bincount(gpv, minlength=n_pv)
+
+
+def pv_metrics(batch, n_pv, pv_z, pv_var, n_reco_tracks=None, min_tracks: int = 5, n_sigma: float = 5.0):
+    """PV efficiency and fake rate (Sec. 3.1: a reconstructed PV matches a
+    simulated one closer than n_sigma times its z uncertainty).  Matching per
+    event, one to one, closest pairs first.  Efficiency counts simulated PVs
+    with at least min_tracks reconstructible particles; a reconstructed PV
+    matched to no simulated PV (of any multiplicity) is a fake."""
+    if n_reco_tracks is None:
+        n_reco_tracks = pv_truth_tracks(batch)
+    E = batch.n_events
+    tz = np.asarray(batch.pv["z"], np.float64)
+    found = np.zeros(len(tz), bool)
+    resid = []
+    n_rec = n_fake = 0
+    for e in range(E):
+        a, b = int(batch.pv_off[e]), int(batch.pv_off[e + 1])
+        k = int(n_pv[e])
+        rz = np.asarray(pv_z[e, :k], np.float64)
+        rs = np.sqrt(np.maximum(np.asarray(pv_var[e, :k], np.float64), 0.0))
+        n_rec += k
+        pairs = sorted((abs(rz[i] - tz[a + j]), i, j) for i in range(k) for j in range(b - a)
+                       if abs(rz[i] - tz[a + j]) < n_sigma * rs[i])
+        used_r, used_t = set(), set()
+        for d, i, j in pairs:
+            if i in used_r or j in used_t:
+                continue
+            used_r.add(i)
+            used_t.add(j)
+            found[a + j] = True
+            resid.append((rz[i] - tz[a + j]) / rs[i])
+        n_fake += k - len(used_r)
+    sel = n_reco_tracks >= min_tracks
+    pulls = np.asarray(resid)
+    return dict(n_true=int(sel.sum()), n_found=int((found & sel).sum()),
+                efficiency=float((found & sel).sum() / max(sel.sum(), 1)),
+                n_rec=n_rec, n_fake=n_fake, fake_rate=n_fake / max(n_rec, 1),
+                pull_mean=float(pulls.mean()) if len(pulls) else 0.0,
+                pull_std=float(pulls.std()) if len(pulls) > 1 else 0.0)

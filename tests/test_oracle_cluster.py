@@ -211,3 +211,35 @@ def test_large_component_without_size_cap(orc):
     cols = np.array([300 + c for r in range(60) for c in range(60)])
     xc = np.average((cols - 767.5) * PITCH, weights=q)
     assert abs(float(h["x"][0]) - xc) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["good", "descent", "overlap", "beyond", "empty"])
+def test_bad_offsets(orc, name):
+    """An event is usable only if offsets[e] <= offsets[e+1] <= n_pixels and no
+    earlier offset exceeds offsets[e]; the others are flagged BAD_OFFSETS and
+    have no hits, and every usable event's hits equal those of the same words
+    clustered alone."""
+    from synth.raw import bad_offsets_case
+    b, cases = bad_offsets_case()
+    offs, exp = cases[name]
+    off = np.array(offs, np.uint64)
+    h = orc.cluster(b.pixels, off)
+    np.testing.assert_array_equal(h["status"], np.array(exp, np.uint32))
+    for e, s in enumerate(exp):
+        a, z = int(off[e]), int(off[e + 1])
+        if s:
+            assert h["n_hits"][e] == 0 and not h["layer_start"][e].any() and not h["layer_nhits"][e].any()
+            continue
+        alone = orc.cluster(b.pixels[a:z], np.array([0, z - a], np.uint64))
+        assert h["n_hits"][e] == alone["n_hits"][0]
+        np.testing.assert_array_equal(h["layer_nhits"][e], alone["layer_nhits"][0])
+        for l in range(26):
+            s0 = int(alone["layer_start"][0, l])
+            m = int(alone["layer_nhits"][0, l])
+            np.testing.assert_array_equal(h["key"][a + s0:a + s0 + m], alone["key"][s0:s0 + m])
+            np.testing.assert_array_equal(h["x"][a + s0:a + s0 + m], alone["x"][s0:s0 + m])
+    # the whole chain accepts the flagged events and gives them no tracks
+    r = orc.reconstruct(b.pixels, off)
+    for e, s in enumerate(exp):
+        if s:
+            assert r["tracks"]["n_tracks"][e] == 0
