@@ -14,13 +14,17 @@
  *     allocated and owned by the caller; the library allocates nothing on
  *     these paths and never synchronises: work is enqueued on `stream` and
  *     the call returns at once.
- *   - Argument errors (null pointer, workspace too small, n_events == 0 with
- *     a null buffer) return VELO_ERR_ARG / VELO_ERR_WORKSPACE before anything
- *     is enqueued.  Content errors are reported per event in status arrays;
+ *   - Argument errors (null pointer, workspace too small, a geometry other
+ *     than the built-in detector model) return VELO_ERR_ARG /
+ *     VELO_ERR_WORKSPACE before anything is enqueued.  Content errors are reported per event in status arrays;
  *     an event with a status bit set contributes no hits and no tracks and
  *     does not affect other events.  Launch failures return VELO_ERR_HIP.
- *   - n_pixels must equal offsets[n_events]; events whose offsets are not
- *     non-decreasing or exceed n_pixels get VELO_EV_BAD_OFFSETS.
+ *   - n_pixels is the length of the pixel buffer (normally offsets[n_events]).
+ *     Event e is usable only if offsets[e] <= offsets[e+1] <= n_pixels and no
+ *     earlier offset exceeds offsets[e]; then no two usable events share a
+ *     word or an output slot.  Any other event gets VELO_EV_BAD_OFFSETS (and
+ *     no other bit), no hits and no tracks; the rest of the batch is
+ *     unaffected.
  *
  * Raw input (the paper's raw data segmented by readout unit, Sec. 2.2):
  *   pixels[n_pixels]  one uint32 word per fired pixel:
@@ -55,6 +59,7 @@ extern "C" {
 typedef enum {
     VELO_OK = 0,
     VELO_ERR_ARG = 1,
+    VELO_ERR_INPUT = 2,      /* velo_check_status: at least one event is flagged */
     VELO_ERR_WORKSPACE = 3,
     VELO_ERR_HIP = 4
 } velo_status;
@@ -66,7 +71,10 @@ enum {
     VELO_EV_DUPLICATE = 4u,    /* two words with one address (reported only if no other bit) */
     VELO_EV_HOLE = 8u,         /* a valid word addresses an inactive (beam-hole) pixel */
     VELO_EV_OVERFLOW = 16u,    /* a track-finding step exceeded VELO_MAX_CANDIDATES */
-    VELO_EV_BAD_OFFSETS = 32u  /* offsets of the event are inconsistent */
+    VELO_EV_BAD_OFFSETS = 32u, /* offsets unusable: decreasing, beyond n_pixels, or below an
+                                  earlier offset (see the conventions above) */
+    VELO_EV_PV_OVERFLOW = 64u  /* vertex finding: more than 2048 admitted tracks (no PVs) or
+                                  more than VELO_MAX_PVS candidates (the first kept) */
 };
 
 /* Cut and filter constants.  The paper fixes only pt0 = 400 MeV for the
@@ -83,6 +91,23 @@ typedef struct {
     float x_over_x0;   /* radiation-length fraction of one plane */
     float qc3, qc4;    /* chi2/ndof limits of 3-hit and >= 4-hit tracks */
 } velo_params;
+
+/* Detector model.  The kernels are built for one model: 26 planes at
+   z = -280 + 1030 l / 25 mm (evaluated in double, rounded once to binary32),
+   1536 x 1536 pixels of 55 um centred on the beam axis, pixels whose centre
+   lies within 5.1 mm of the axis inactive.  Every call that decodes pixels or
+   uses plane positions takes the caller's statement of the model and
+   returns VELO_ERR_ARG before enqueuing anything when it differs from the
+   built-in one (field by field, plane positions bit for bit), so a caller
+   with another detector cannot silently get results for this one.        */
+typedef struct {
+    int32_t n_layers;        /* 26 */
+    float z_mm[26];          /* plane positions */
+    float pitch_mm;          /* 0.055 */
+    int32_t n_cols, n_rows;  /* 1536, 1536 */
+    float hole_r_mm;         /* 5.1 */
+} velo_geometry;
+void velo_geometry_default(velo_geometry* g);
 
 /* Hits: the output of velo_cluster.  Capacity n_pixels slots.
    Hits of plane l of event e occupy slots offsets[e] + layer_start[27e+l] + k,
@@ -164,7 +189,7 @@ size_t velo_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
    the pixel centres computed from integer sums, (float)sum(q c)/(float)sum(q),
    in binary32.  Fills every array of `out`.                                 */
 velo_status velo_cluster(const uint32_t* d_pixels, const uint64_t* d_offsets, uint32_t n_events,
-                         uint64_t n_pixels, const velo_hits* out, void* d_ws, size_t ws_bytes,
+                         uint64_t n_pixels, const velo_geometry* geom, const velo_hits* out, void* d_ws, size_t ws_bytes,
                          hipStream_t stream);
 
 /* Track finding by triplet seeding and forwarding (paper Sec. 2.3.1, second
@@ -177,7 +202,7 @@ velo_status velo_cluster(const uint32_t* d_pixels, const uint64_t* d_offsets, ui
    accepted greedily by (s, key1, key0, key2).  Each hit joins at most one
    track.  Reads hits from velo_cluster; fills `out`.                        */
 velo_status velo_find_tracks(const velo_hits* hits, const uint64_t* d_offsets, uint32_t n_events,
-                             uint64_t n_pixels, const velo_params* params, const velo_tracks* out,
+                             uint64_t n_pixels, const velo_geometry* geom, const velo_params* params, const velo_tracks* out,
                              void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* Simple Kalman filter per projection, x and y independent, with multiple
@@ -189,25 +214,41 @@ velo_status velo_find_tracks(const velo_hits* hits, const uint64_t* d_offsets, u
    nhits is outside [3, 26] or whose hit_idx points outside its event is
    skipped (its state is left as it was).                                    */
 velo_status velo_fit(const velo_hits* hits, const velo_tracks* tracks, const uint64_t* d_offsets,
-                     uint32_t n_events, uint64_t n_pixels, const velo_params* params,
+                     uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                     const velo_params* params,
                      const velo_states* out, hipStream_t stream);
 
 /* velo_cluster, velo_find_tracks and velo_fit enqueued back to back. */
 velo_status velo_reconstruct(const uint32_t* d_pixels, const uint64_t* d_offsets, uint32_t n_events,
-                             uint64_t n_pixels, const velo_params* params, const velo_hits* hits,
+                             uint64_t n_pixels, const velo_geometry* geom, const velo_params* params, const velo_hits* hits,
                              const velo_tracks* tracks, const velo_states* states, void* d_ws,
                              size_t ws_bytes, hipStream_t stream);
+
+/* Measurement hook: velo_reconstruct with HIP events recorded on `stream`
+   around the main kernel of each stage, for timing a kernel by itself:
+   ev6[0], ev6[1] around the clustering kernel of the (event, plane) segments,
+   ev6[2], ev6[3] around the per-event track-finding kernel, ev6[4], ev6[5]
+   around the fit kernel.  Null entries are not recorded; the results equal
+   velo_reconstruct's.                                                       */
+velo_status velo_reconstruct_timed(const uint32_t* d_pixels, const uint64_t* d_offsets,
+                                   uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                                   const velo_params* params,
+                                   const velo_hits* hits, const velo_tracks* tracks,
+                                   const velo_states* states, void* d_ws, size_t ws_bytes,
+                                   hipStream_t stream, const hipEvent_t* ev6);
 
 /* velo_fit followed by the classifier in the same kernel: bfloat16 (round to
    nearest even) weights and activations into matrix-core instructions with
    binary32 accumulation; writes score (logit) and accepted.                */
 velo_status velo_fit_mlp(const velo_hits* hits, const velo_tracks* tracks, const uint64_t* d_offsets,
-                         uint32_t n_events, uint64_t n_pixels, const velo_params* params,
+                         uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                         const velo_params* params,
                          const velo_mlp* mlp, const velo_states* out, hipStream_t stream);
 
 /* velo_cluster, velo_find_tracks and velo_fit_mlp enqueued back to back. */
 velo_status velo_reconstruct_mlp(const uint32_t* d_pixels, const uint64_t* d_offsets,
-                                 uint32_t n_events, uint64_t n_pixels, const velo_params* params,
+                                 uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                                 const velo_params* params,
                                  const velo_mlp* mlp, const velo_hits* hits,
                                  const velo_tracks* tracks, const velo_states* states, void* d_ws,
                                  size_t ws_bytes, hipStream_t stream);
@@ -216,7 +257,8 @@ velo_status velo_reconstruct_mlp(const uint32_t* d_pixels, const uint64_t* d_off
    capacity floor(n_pixels/3) slots; needs states from velo_fit.           */
 velo_status velo_track_features(const velo_hits* hits, const velo_tracks* tracks,
                                 const velo_states* states, const uint64_t* d_offsets,
-                                uint32_t n_events, uint64_t n_pixels, float* d_feat,
+                                uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                                float* d_feat,
                                 hipStream_t stream);
 
 /* Workspace of velo_feature_stats / velo_mlp_fwd_bwd for n samples. */
@@ -263,17 +305,37 @@ velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n,
    graph with the context's current shapes (no tuning, no graph of its own).
    The context owns the tuned configuration and the graphs; calls on one
    context must not overlap (one host thread at a time).  d_ws:
-   velo_batched_workspace_bytes bytes.                                      */
+   velo_batched_workspace_bytes bytes.  With mlp == NULL the context's own
+   classifier applies if one was loaded (velo_mlp_load), else the plain cut. */
 typedef struct velo_context velo_context;
-velo_status velo_context_create(velo_context** ctx);
+/* The context keeps the geometry (checked here) and the parameters, which
+   velo_reconstruct_batched uses when its params argument is NULL.        */
+velo_status velo_context_create(velo_context** ctx, const velo_geometry* geom,
+                                const velo_params* params);
 void velo_context_destroy(velo_context* ctx);
-/* out6 = {tuned, clustering grid (0 = one workgroup per segment), large-segment
-   grid, track-finding lanes per event, track-finding grid (0 = one workgroup
-   per event), fit lanes per event}; tuned_ms5 (may be NULL) = tuning-stream
-   times of the chosen clustering, track-finding and fit shapes, then the best
-   clustering time with one workgroup per segment and the best track-finding
-   time with one workgroup per event.                                       */
+/* out6 = {how the shapes were chosen (0 not yet, 1 tuned on this context's
+   first batch, 2 taken from the process-wide tune cache, 3 set by
+   velo_context_set_config), clustering grid (0 = one workgroup per segment),
+   large-segment grid, track-finding lanes per event, track-finding grid
+   (0 = one workgroup per event), fit lanes per event}; tuned_ms5 (may be
+   NULL) = tuning-stream times of the chosen clustering, track-finding and fit
+   shapes, then the best clustering time with one workgroup per segment and
+   the best track-finding time with one workgroup per event (zeros when set
+   by the caller).
+   The tuned shapes are kept in a process-wide cache (64 entries) keyed by
+   the device architecture, the event count and mean words per event (in
+   quarter-octave classes), the classifier flag and the parameters: a new
+   context whose first batch falls in a cached class takes the shapes from
+   there without timing anything.                                           */
 velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms5);
+/* Fix the launch shapes of a context instead of tuning them (for callers that
+   know their workload, and for tests that run every shape):
+   in5 = {clustering grid 0..65536 (0 = one workgroup per segment),
+   large-segment grid 1..65536, track-finding lanes 128 or 256, track-finding
+   grid 0..65536 (0 = one workgroup per event), fit lanes 64, 128 or 256}.
+   Other values return VELO_ERR_ARG and leave the context unchanged.  Drops
+   the context's captured graphs; results do not depend on the shapes.      */
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in5);
 size_t velo_batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
 velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels,
                                      const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
@@ -281,6 +343,153 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
                                      const velo_hits* hits, const velo_tracks* tracks,
                                      const velo_states* states, void* d_ws, size_t ws_bytes,
                                      hipStream_t stream);
+
+/* Classifier held by a batched-form context.  velo_mlp_load copies a
+   network into device memory the context owns (allocated on the first load)
+   and resets its Adam moments; from then on velo_reconstruct_batched with
+   mlp == NULL applies it (fused after the fit, as with an explicit mlp;
+   states->score is then required).  Blob (VELO_MLP_BLOB_BYTES, host
+   memory, little-endian): uint32 magic 0x504C4D56 ("VMLP"), uint32 version
+   1, uint32 1377, uint32 8, then binary32 params[1377], mean[8], std[8]
+   (each > 0), threshold; every value finite, else VELO_ERR_ARG with the
+   context unchanged.  Load and save synchronise the device.               */
+#define VELO_MLP_BLOB_MAGIC 0x504C4D56u
+#define VELO_MLP_BLOB_BYTES (16u + 4u * (VELO_MLP_PARAMS + 2u * VELO_MLP_FEATURES + 1u))
+typedef struct velo_context velo_context;
+velo_status velo_mlp_load(velo_context* ctx, const void* h_blob, size_t bytes);
+velo_status velo_mlp_save(const velo_context* ctx, void* h_blob, size_t bytes);
+/* One training step of the context's classifier on the GPU: the FP32 forward
+   and backward pass of velo_mlp_fwd_bwd over n samples (rows d_idx[i], or
+   rows 0..n-1 when d_idx is NULL, of d_feat with labels d_label), then the
+   Adam update of velo_mlp_adam_step with this step number (>= 1) and
+   learning rate.  The mean loss goes to d_loss (may be NULL).  Needs a
+   loaded network; grows the context's workspace (a device allocation) the
+   first time a larger n is seen.  Asynchronous on `stream`.               */
+velo_status velo_mlp_train_step(velo_context* ctx, const float* d_feat, const float* d_label,
+                                const uint32_t* d_idx, uint32_t n, float lr, uint32_t step,
+                                float* d_loss, hipStream_t stream);
+
+/* Synchronous check of per-event status arrays (either may be NULL, e.g.
+   hits.status and tracks.status): the OR of all their words over n_events
+   goes to *h_or (d_word: one device word of scratch).  Synchronises
+   `stream`; returns VELO_ERR_INPUT if any bit is set, else VELO_OK.       */
+velo_status velo_check_status(const uint32_t* d_status_a, const uint32_t* d_status_b, uint32_t n_events,
+                              uint32_t* d_word, uint32_t* h_or, hipStream_t stream);
+
+/* Primary vertices (paper Sec. 2.3.1, last paragraph): PV candidates are
+   peaks of a histogram of the tracks' beamline z, and every candidate is
+   fitted with every track, the track's weight shared among the candidates,
+   so the candidates are fitted in parallel.
+     admission   accepted tracks with tx^2 + ty^2 >= 1e-6, beamline-z variance
+                 var = (tx^2 var_x + ty^2 var_y) / (tx^2 + ty^2)^2 in
+                 (0, max_var], z in [z0, z0 + n_bins bin_w); at most 2048 per
+                 event (more: VELO_EV_PV_OVERFLOW and no PVs)
+     histogram   a track in bin b = floor((z - z0) / bin_w) adds 2 to b and
+                 1 to b - 1 and b + 1
+     candidates  bins with count >= seed_min, above the nms bins before and
+                 at least the nms bins after; seeded at the bin centre
+     fit         n_iter rounds, all candidates at once: chi2 = (z - z_v)^2 /
+                 var, r = (1 - chi2/chi2_cut)^2 below the cut (else 0),
+                 w = r * (r / sum of the track's r over the candidates),
+                 z_v = sum(w z / var) / sum(w / var)
+     output      var_v = 1 / sum(w / var) and weight sum W_v = sum(w) at the
+                 final positions; PVs are the candidates with W_v >=
+                 min_weight, in increasing seed z.
+   Sums run over tracks in slot order and over candidates in order, in
+   binary32 without contraction: results are reproducible bit for bit.    */
+#define VELO_MAX_PVS 64
+typedef struct {
+    float z0;          /* mm, lower edge of the histogram (-256) */
+    float bin_w;       /* mm, bin width (0.5) */
+    int32_t n_bins;    /* 1..1024 (1024) */
+    float max_var;     /* mm^2, largest admitted beamline-z variance (4) */
+    int32_t seed_min;  /* smallest count of a candidate bin (8) */
+    int32_t nms;       /* bins on each side a candidate dominates, 0..64 (2) */
+    float chi2_cut;    /* Tukey cut (9) */
+    int32_t n_iter;    /* fit rounds, 0..64 (8) */
+    float min_weight;  /* smallest weight sum of a PV (3) */
+} velo_pv_params;
+void velo_pv_params_default(velo_pv_params* p);
+/* Output, per event: n_pv[e]; z, var (variance of z) and weight (weight sum)
+   of PV k at e * VELO_MAX_PVS + k, zero beyond n_pv[e]; status[e] = 0 or
+   VELO_EV_PV_OVERFLOW.                                                      */
+typedef struct {
+    uint32_t* n_pv;   /* [n_events] */
+    float* z;         /* [n_events * VELO_MAX_PVS] */
+    float* var;
+    float* weight;
+    uint32_t* status; /* [n_events] */
+} velo_pvs;
+/* Reads the fitted states (z, tx, ty, cov_x[0], cov_y[0], accepted) of the
+   track slots of every event (counts clamped like velo_fit's); one workgroup
+   per event, no workspace.                                                 */
+velo_status velo_find_pvs(const velo_tracks* tracks, const velo_states* states,
+                          const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
+                          const velo_pv_params* params, const velo_pvs* out, hipStream_t stream);
+
+/* Streaming form (paper Sec. 2.2: raw events are copied to the GPU and only
+   tracks and vertices come back; Sec. 3.2: several host-thread / GPU-stream
+   pairs keep transfers and kernels of different batches overlapped).
+   A pipeline owns n_streams slots, each a host thread with its own HIP
+   stream, pinned host staging and device buffers for one batch of at most
+   events_per_batch events and words_per_batch raw words.  velo_pipeline_run
+   takes raw events in ordinary host memory and
+     - applies the global event cut on the host: an event with more raw
+       words than gec_max_words (0: no cut), or more than words_per_batch,
+       gets VELO_EV_GEC and is not processed (Sec. 2.3: the busiest events
+       are removed before the sequence); an event whose host offsets break
+       the usable-offsets rule gets VELO_EV_BAD_OFFSETS;
+     - packs the remaining events into batches, batch k on slot k mod
+       n_streams; per batch: copy in, velo_reconstruct (or
+       velo_reconstruct_mlp with the pipeline's classifier), velo_find_pvs,
+       gather the tracks into dense rows, copy back counts, statuses and
+       vertices, then exactly the rows that exist;
+     - fills the caller's result: per event its status (clustering, track
+       finding and vertex bits, or VELO_EV_GEC), its track count and the
+       index of its first row in `tracks`, and its vertices.  Rows of one
+       event are contiguous and in the event's track order; the order of
+       the batches in the table depends on which slot finishes first.
+   Returns after every slot has finished (synchronous); VELO_ERR_WORKSPACE
+   if the rows exceed track_capacity (total raw words / 3 always suffices).
+   The pipeline allocates its buffers at creation (about 0.7 GB per slot
+   for 1000 events of nominal occupancy); runs of one pipeline must not
+   overlap.                                                                */
+#define VELO_EV_GEC 128u
+typedef struct {
+    int32_t n_streams;          /* slots (host-thread / stream pairs), 1..32 */
+    uint32_t events_per_batch;  /* 1..VELO_MAX_EVENTS */
+    uint64_t words_per_batch;   /* raw-word capacity of a batch */
+    uint32_t gec_max_words;     /* global event cut: most raw words of an event (0: none) */
+} velo_pipeline_config;
+typedef struct {
+    float x, y, z, tx, ty, chi2;  /* beamline state and chi2 */
+    int32_t ndof;
+    uint8_t accepted;             /* quality decision (plain cut or classifier) */
+    uint8_t nhits;
+    uint16_t pad;
+} velo_track_row;                 /* 32 bytes */
+typedef struct {
+    uint32_t* status;        /* [n_events] */
+    uint32_t* n_tracks;      /* [n_events] */
+    uint64_t* first_track;   /* [n_events] */
+    velo_track_row* tracks;  /* [track_capacity] */
+    uint64_t track_capacity;
+    uint32_t* n_pv;          /* [n_events], NULL: vertices not copied out */
+    float* pv_z;             /* [n_events * VELO_MAX_PVS] */
+    float* pv_var;           /* [n_events * VELO_MAX_PVS] */
+} velo_pipeline_result;
+typedef struct velo_pipeline velo_pipeline;
+/* mlp (device pointers, kept valid by the caller for the pipeline's life)
+   may be NULL: plain cut; pv_params NULL: velo_pv_params_default.        */
+velo_status velo_pipeline_create(velo_pipeline** out, const velo_pipeline_config* cfg,
+                                 const velo_geometry* geom, const velo_params* params, const velo_mlp* mlp,
+                                 const velo_pv_params* pv_params);
+void velo_pipeline_destroy(velo_pipeline* p);
+/* h_pixels[n_pixels], h_offsets[n_events + 1]: host memory; *n_rows receives
+   the number of rows written.                                             */
+velo_status velo_pipeline_run(velo_pipeline* p, const uint32_t* h_pixels, uint64_t n_pixels,
+                              const uint64_t* h_offsets, uint32_t n_events,
+                              const velo_pipeline_result* out, uint64_t* n_rows);
 
 const char* velo_status_string(velo_status s);
 

@@ -196,8 +196,8 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
     const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
     if (mode)
       hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
-    hipLaunchKernelGGL(k_validate, dim3(c.n_events), dim3(kValThreads), 0, s, c.px, c.offsets,
-                       c.n_pixels, c.hits.status, c.hits.layer_start, (uint32_t*)c.ws);
+    launch_validate(c.px, c.offsets, c.n_events, c.n_pixels, c.hits.status, c.hits.layer_start,
+                    (uint32_t*)c.ws, s);
     // size orders for the persistent kernels that use them
     if (mode) {
       const uint32_t og = (order_items(c.n_events, mode) + kOrderThreads - 1) / kOrderThreads;
@@ -232,7 +232,19 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
 // ---------------------------------------------------------------------------
 
 struct velo_context {
+  // classifier held by the context (velo_mlp_load): params[1377], mean[8],
+  // std[8] in one device buffer, Adam moments, gradient, loss, workspace
+  float* net = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* grad = nullptr;
+  float* loss = nullptr;
+  void* mlp_ws = nullptr;
+  size_t mlp_ws_bytes = 0;
+  float threshold = 0.0f;
+  velo_params params{};  // used when a call passes no parameters
   bool tuned = false;
+  int source = 0;  // how cfg was chosen: 1 tuned here, 2 tune cache, 3 set by the caller
   velo::BatchedCfg cfg{2048, 512, 256, 1024, 128};
   float tuned_ms[5] = {0, 0, 0, 0, 0};
   // captured graphs of recent call shapes (buffers, sizes, parameters, stream)

@@ -4,6 +4,8 @@
 // here a region is one (event, plane) segment of the raw buffer).
 //
 // Pipeline (all on one stream, no host round trip):
+//   k_offsets   one workgroup: events whose offsets are unusable (decreasing,
+//               beyond the buffer, or overlapping an earlier event's words)
 //   k_validate  one workgroup per event: bad word / hole / plane-order flags
 //               and the plane boundaries (layer_start) of the event; clears
 //               the large-segment work list
@@ -305,11 +307,50 @@ __device__ __forceinline__ void validate_words(const uint32_t* __restrict__ w, u
   if (flags) atomicOr(flags_out, flags);
 }
 
+// Usable offsets: event e owns words [offsets[e], offsets[e+1]) only if
+// offsets[e] <= offsets[e+1] <= n_pixels and no earlier offset exceeds
+// offsets[e] (offsets[e] is the running maximum of offsets[0..e]); then the
+// word ranges of usable events are disjoint.  One 1024-lane workgroup walks
+// the offsets in tiles of 1024 events, carrying the running maximum from tile
+// to tile, and writes status[e] = 0 or VELO_EV_BAD_OFFSETS.
+constexpr int kOffThreads = 1024;
+__global__ __launch_bounds__(kOffThreads) void k_offsets(const uint64_t* __restrict__ offsets,
+                                                         uint32_t n_events, uint64_t n_pixels,
+                                                         uint32_t* __restrict__ status) {
+  __shared__ uint64_t wmax[2][kOffThreads / kWave];
+  const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint64_t carry = 0;  // largest offset before the tile
+  int buf = 0;
+  for (uint32_t t0 = 0; t0 < n_events; t0 += kOffThreads, buf ^= 1) {
+    const uint32_t e = t0 + threadIdx.x;
+    const bool in = e < n_events;
+    const uint64_t a = in ? offsets[e] : 0, b = in ? offsets[e + 1] : 0;
+    uint64_t x = a;  // inclusive running maximum over the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint64_t y = __shfl_up(x, d, kWave);
+      if ((int)lane >= d) x = x > y ? x : y;
+    }
+    if (lane == kWave - 1) wmax[buf][wid] = x;
+    __syncthreads();  // (the other buffer serves the next tile)
+    uint64_t before = carry, tile = carry;
+    for (uint32_t w = 0; w < kOffThreads / kWave; ++w) {
+      const uint64_t v = wmax[buf][w];
+      if (w < wid) before = before > v ? before : v;
+      tile = tile > v ? tile : v;
+    }
+    const uint64_t left = __shfl_up(x, 1, kWave);  // lanes before this one
+    if (lane > 0) before = before > left ? before : left;
+    if (in) status[e] = (a > b || b > n_pixels || a < before) ? VELO_EV_BAD_OFFSETS : 0u;
+    carry = tile;
+  }
+}
+
 // One workgroup per event: flags of every word (status[e], written whole)
 // and the plane boundaries of the event (layer_start[27e + l] = index of the
 // first word of plane >= l); workgroup 0 also clears the large-segment list.
-// Events never share a word, so overlapping or inconsistent offsets of one
-// event cannot disturb another (inconsistent ones are flagged by k_finalize).
+// Runs after k_offsets: an event it flagged is left as it is, and usable
+// events never share a word, so one event's words cannot disturb another.
 __global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __restrict__ px,
                                                           const uint64_t* __restrict__ offsets,
                                                           uint64_t n_pixels,
@@ -318,16 +359,26 @@ __global__ __launch_bounds__(kValThreads) void k_validate(const uint32_t* __rest
                                                           uint32_t* __restrict__ mid_count) {
   __shared__ uint32_t s_flags;
   const uint32_t e = blockIdx.x;
+  const uint32_t st0 = status[e];
   if (threadIdx.x == 0) {
     s_flags = 0;
     if (e == 0) *mid_count = 0;
   }
   __syncthreads();
   const uint64_t b = offsets[e], end = offsets[e + 1];
-  if (b <= end && end <= n_pixels)
+  if (st0 == 0 && b <= end && end <= n_pixels)
     validate_words(px + b, (uint32_t)(end - b), layer_start + 27ull * e, &s_flags);
   __syncthreads();
-  if (threadIdx.x == 0) status[e] = s_flags;
+  if (threadIdx.x == 0) status[e] = s_flags | st0;
+}
+
+// offsets check, then word validation (both orders of events are free)
+inline void launch_validate(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
+                            uint64_t n_pixels, uint32_t* status, uint32_t* layer_start,
+                            uint32_t* mid_count, hipStream_t s) {
+  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(kOffThreads), 0, s, offsets, n_events, n_pixels, status);
+  hipLaunchKernelGGL(k_validate, dim3(n_events), dim3(kValThreads), 0, s, px, offsets, n_pixels,
+                     status, layer_start, mid_count);
 }
 
 // offsets of event e are usable (monotone and inside the buffer)
@@ -455,7 +506,7 @@ __global__ void k_finalize(const uint64_t* __restrict__ offsets, uint32_t n_even
                            uint32_t* __restrict__ n_hits) {
   uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_events) return;
-  uint32_t st = status[e];
+  uint32_t st = status[e];  // VELO_EV_BAD_OFFSETS from k_offsets stands alone
   const bool ok = event_ok(offsets, e, n_pixels);
   if (!ok) st = VELO_EV_BAD_OFFSETS;
   const bool empty = ok && offsets[e + 1] == offsets[e];
@@ -491,9 +542,11 @@ size_t cluster_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
   return up(4) + up(4ull * kLayers * n_events) + up(5ull * 4 * n_pixels) + up(8ull * n_pixels);
 }
 
+// ev (may be null): events recorded just before and after the per-segment kernel
 hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint32_t n_events,
                               uint64_t n_pixels, const velo_hits* h, void* ws, hipStream_t s,
-                              const ClusterCfg& cfg, bool validated = false) {
+                              const ClusterCfg& cfg, bool validated = false,
+                              const hipEvent_t* ev = nullptr) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   char* base = (char*)ws;
   uint32_t* mid_count = (uint32_t*)base;
@@ -502,14 +555,15 @@ hipError_t launch_cluster_cfg(const uint32_t* px, const uint64_t* offsets, uint3
   uint64_t* scratch64 = (uint64_t*)((char*)scratch + up(5ull * 4 * n_pixels));
   HitsOut o{h->x, h->y, h->key, h->aux};
   if (!validated)
-    hipLaunchKernelGGL(k_validate, dim3(n_events), dim3(kValThreads), 0, s, px, offsets, n_pixels,
-                       h->status, h->layer_start, mid_count);
+    launch_validate(px, offsets, n_events, n_pixels, h->status, h->layer_start, mid_count, s);
   SmallArgs a{px, offsets, n_pixels, h->status, h->layer_start, h->layer_nhits, o, mid_count, mid_list};
+  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
   if (cfg.small_grid == 0)
     hipLaunchKernelGGL(k_small, dim3(n_events * kLayers), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(k_small_ws, dim3(cfg.small_grid), dim3(64), 0, s, a, cfg.seg_order,
                        n_events * kLayers, cfg.counters);
+  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_mid, dim3(cfg.mid_grid), dim3(kMidThreads), 0, s, px, offsets, h->layer_start,
                      h->layer_nhits, o, mid_count, mid_list, scratch, scratch64, n_pixels,
                      cfg.small_grid ? cfg.counters + 1 : (uint32_t*)nullptr);

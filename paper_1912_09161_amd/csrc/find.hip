@@ -1134,9 +1134,10 @@ struct FindCfg {
   uint32_t* counters;         // [3] zeroed work-stealing counters (work stealing)
 };
 
+// ev (may be null): events recorded just before and after the per-event kernel
 hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
                            uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
-                           hipStream_t s, const FindCfg& cfg) {
+                           hipStream_t s, const FindCfg& cfg, const hipEvent_t* ev = nullptr) {
   FindWs f;
   find_ws_layout((char*)ws, n_pixels, n_events, &f);
   FindArgs a{f.xs, f.ys, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
@@ -1149,12 +1150,14 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
   const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
   uint32_t* steal = ws_mode ? cfg.counters : nullptr;
+  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
   if (cfg.small_threads == 128)
     hipLaunchKernelGGL((k_find_lds<128, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(128), 0, s, a, c,
                        n_events, order, (const uint32_t*)nullptr, steal);
   else
     hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(kSThreads),
                        0, s, a, c, n_events, order, (const uint32_t*)nullptr, steal);
+  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
   FindArgs a2 = a;
   a2.esc_count = f.esc2_count;
   a2.esc_list = f.esc2_list;

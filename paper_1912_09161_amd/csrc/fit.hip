@@ -250,13 +250,17 @@ static void fit_kernels(const velo_hits* h, const velo_tracks* t, const uint64_t
 }
 
 // threads: 64, 128 or 256 lanes per event (the batched form's autotuner picks it)
+// ev (may be null): events recorded just before and after the fit kernel
 hipError_t launch_fit_cfg(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
                           uint32_t n_events, uint64_t n_pixels, const velo_params* p,
-                          const velo_mlp* m, const velo_states* o, hipStream_t s, int threads) {
+                          const velo_mlp* m, const velo_states* o, hipStream_t s, int threads,
+                          const hipEvent_t* ev = nullptr) {
   const FitConst c = make_fit_const(p);
+  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
   if (threads == 64) fit_kernels<64>(h, t, offsets, n_events, n_pixels, c, m, o, s);
   else if (threads == 256) fit_kernels<256>(h, t, offsets, n_events, n_pixels, c, m, o, s);
   else fit_kernels<kFitThreads>(h, t, offsets, n_events, n_pixels, c, m, o, s);
+  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
   return hipGetLastError();
 }
 

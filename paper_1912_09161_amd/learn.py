@@ -40,7 +40,7 @@ class Trainer:
     and standard deviation."""
 
     def __init__(self, feat: torch.Tensor, label: torch.Tensor, seed: int = 0, lr: float = 1e-3,
-                 batch: int = 4096, mean=None, std=None):
+                 batch: int = 4096, mean=None, std=None, ghost_weight: float = 1.0):
         assert feat.dtype == torch.float32 and feat.dim() == 2 and feat.shape[1] == velo.N_FEATURES
         self.feat = feat.contiguous()
         self.label = label.to(torch.float32).contiguous()
@@ -56,14 +56,22 @@ class Trainer:
         self.v = torch.zeros_like(self.params)
         self.step = 0
         self.rng = np.random.default_rng(seed + 1)
+        # an epoch visits every track once and every ghost (label 0) about
+        # ghost_weight times: the rare class weighted by repetition, which in
+        # expectation is the loss with weight ghost_weight on ghosts
+        self.rows = np.arange(self.n, dtype=np.int32)
+        reps = int(round(ghost_weight)) - 1
+        if reps > 0:
+            ghosts = np.nonzero(self.label.cpu().numpy() == 0)[0].astype(np.int32)
+            self.rows = np.concatenate([self.rows] + [ghosts] * reps)
         self.ws = velo.mlp_workspace(batch, self.dev)
         self.grad = torch.empty(velo.N_PARAMS, dtype=torch.float32, device=self.dev)
         self.loss = torch.empty(1, dtype=torch.float32, device=self.dev)
 
     def epoch(self) -> float:
-        perm = torch.from_numpy(self.rng.permutation(self.n).astype(np.int32)).to(self.dev)
+        perm = torch.from_numpy(self.rng.permutation(self.rows).astype(np.int32)).to(self.dev)
         losses = []
-        for b0 in range(0, self.n, self.batch):
+        for b0 in range(0, perm.numel(), self.batch):
             idx = perm[b0:b0 + self.batch]
             nb = idx.numel()
             velo.mlp_fwd_bwd(self.params, self.mean, self.std, self.feat, self.label, nb, idx=idx,

@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +38,11 @@ class Params(C.Structure):
                 ("s_fwd", C.c_float), ("max_skip", C.c_int32), ("sigma_meas", C.c_float),
                 ("pt0_mev", C.c_float), ("x_over_x0", C.c_float), ("qc3", C.c_float),
                 ("qc4", C.c_float)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("z_mm", C.c_float * 26), ("pitch_mm", C.c_float),
+                ("n_cols", C.c_int32), ("n_rows", C.c_int32), ("hole_r_mm", C.c_float)]
 
 
 class _Hits(C.Structure):
@@ -79,23 +85,45 @@ def lib():
         P = C.c_void_p
         L.velo_params_default.argtypes = [P]
         L.velo_params_default.restype = None
+        L.velo_geometry_default.argtypes = [P]
+        L.velo_geometry_default.restype = None
         L.velo_workspace_bytes.argtypes = [C.c_uint64, C.c_uint32]
         L.velo_workspace_bytes.restype = C.c_size_t
-        L.velo_cluster.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, C.c_size_t, P]
+        L.velo_cluster.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, C.c_size_t, P]
         L.velo_cluster.restype = C.c_int
-        L.velo_find_tracks.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, C.c_size_t, P]
+        L.velo_find_tracks.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, C.c_size_t, P]
         L.velo_find_tracks.restype = C.c_int
-        L.velo_fit.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P]
+        L.velo_fit.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P]
         L.velo_fit.restype = C.c_int
-        L.velo_reconstruct.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, C.c_size_t, P]
+        L.velo_reconstruct.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
         L.velo_reconstruct.restype = C.c_int
+        L.velo_pv_params_default.argtypes = [P]
+        L.velo_pv_params_default.restype = None
+        L.velo_find_pvs.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P]
+        L.velo_find_pvs.restype = C.c_int
+        L.velo_pipeline_create.argtypes = [P, P, P, P, P, P]
+        L.velo_pipeline_create.restype = C.c_int
+        L.velo_pipeline_destroy.argtypes = [P]
+        L.velo_pipeline_destroy.restype = None
+        L.velo_pipeline_run.argtypes = [P, P, C.c_uint64, P, C.c_uint32, P, P]
+        L.velo_pipeline_run.restype = C.c_int
+        L.velo_reconstruct_timed.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P, P]
+        L.velo_reconstruct_timed.restype = C.c_int
+        L.velo_mlp_load.argtypes = [P, P, C.c_size_t]
+        L.velo_mlp_load.restype = C.c_int
+        L.velo_mlp_save.argtypes = [P, P, C.c_size_t]
+        L.velo_mlp_save.restype = C.c_int
+        L.velo_mlp_train_step.argtypes = [P, P, P, P, C.c_uint32, C.c_float, C.c_uint32, P, P]
+        L.velo_mlp_train_step.restype = C.c_int
+        L.velo_check_status.argtypes = [P, P, C.c_uint32, P, P, P]
+        L.velo_check_status.restype = C.c_int
         L.velo_status_string.argtypes = [C.c_int]
         L.velo_status_string.restype = C.c_char_p
-        L.velo_fit_mlp.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P]
+        L.velo_fit_mlp.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P, P]
         L.velo_fit_mlp.restype = C.c_int
-        L.velo_reconstruct_mlp.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
+        L.velo_reconstruct_mlp.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, P, C.c_size_t, P]
         L.velo_reconstruct_mlp.restype = C.c_int
-        L.velo_track_features.argtypes = [P, P, P, P, C.c_uint32, C.c_uint64, P, P]
+        L.velo_track_features.argtypes = [P, P, P, P, C.c_uint32, C.c_uint64, P, P, P]
         L.velo_track_features.restype = C.c_int
         L.velo_mlp_workspace_bytes.argtypes = [C.c_uint32]
         L.velo_mlp_workspace_bytes.restype = C.c_size_t
@@ -107,12 +135,14 @@ def lib():
         L.velo_mlp_adam_step.restype = C.c_int
         L.velo_mlp_infer.argtypes = [P, P, C.c_uint32, P, P]
         L.velo_mlp_infer.restype = C.c_int
-        L.velo_context_create.argtypes = [P]
+        L.velo_context_create.argtypes = [P, P, P]
         L.velo_context_create.restype = C.c_int
         L.velo_context_destroy.argtypes = [P]
         L.velo_context_destroy.restype = None
         L.velo_context_config.argtypes = [P, P, P]
         L.velo_context_config.restype = C.c_int
+        L.velo_context_set_config.argtypes = [P, P]
+        L.velo_context_set_config.restype = C.c_int
         L.velo_batched_workspace_bytes.argtypes = [C.c_uint64, C.c_uint32]
         L.velo_batched_workspace_bytes.restype = C.c_size_t
         L.velo_reconstruct_batched.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P,
@@ -120,6 +150,25 @@ def lib():
         L.velo_reconstruct_batched.restype = C.c_int
         _lib = L
     return _lib
+
+
+_GEOM = None
+
+
+def default_geometry() -> Geometry:
+    """The detector model the kernels are built for (velo_geometry_default)."""
+    g = Geometry()
+    lib().velo_geometry_default(C.byref(g))
+    return g
+
+
+def _geom(g=None):
+    global _GEOM
+    if g is not None:
+        return C.byref(g)
+    if _GEOM is None:
+        _GEOM = default_geometry()
+    return C.byref(_GEOM)
 
 
 def default_params(**overrides) -> Params:
@@ -207,7 +256,7 @@ def cluster(pixels: torch.Tensor, offsets: torch.Tensor, hits=None, ws=None, str
     hits = hits if hits is not None else alloc_hits(N, E, pixels.device)
     ws = ws if ws is not None else alloc_workspace(N, E, pixels.device)
     hs = _hits_struct(hits)
-    _check(lib().velo_cluster(_ptr(pixels), _ptr(offsets), E, N, C.byref(hs), _ptr(ws),
+    _check(lib().velo_cluster(_ptr(pixels), _ptr(offsets), E, N, _geom(), C.byref(hs), _ptr(ws),
                               ws.numel(), _stream(stream)))
     return hits
 
@@ -219,7 +268,7 @@ def find_tracks(hits: dict, offsets: torch.Tensor, n_pixels: int, params=None, t
     tracks = tracks if tracks is not None else alloc_tracks(n_pixels, E, offsets.device)
     ws = ws if ws is not None else alloc_workspace(n_pixels, E, offsets.device)
     hs, ts = _hits_struct(hits), _tracks_struct(tracks)
-    _check(lib().velo_find_tracks(C.byref(hs), _ptr(offsets), E, int(n_pixels), C.byref(params),
+    _check(lib().velo_find_tracks(C.byref(hs), _ptr(offsets), E, int(n_pixels), _geom(), C.byref(params),
                                   C.byref(ts), _ptr(ws), ws.numel(), _stream(stream)))
     return tracks
 
@@ -230,7 +279,7 @@ def fit(hits: dict, tracks: dict, offsets: torch.Tensor, n_pixels: int, params=N
     params = params if params is not None else default_params()
     states = states if states is not None else alloc_states(n_pixels, offsets.device)
     hs, ts, ss = _hits_struct(hits), _tracks_struct(tracks), _states_struct(states)
-    _check(lib().velo_fit(C.byref(hs), C.byref(ts), _ptr(offsets), E, int(n_pixels),
+    _check(lib().velo_fit(C.byref(hs), C.byref(ts), _ptr(offsets), E, int(n_pixels), _geom(),
                           C.byref(params), C.byref(ss), _stream(stream)))
     return states
 
@@ -248,8 +297,170 @@ def reconstruct(pixels: torch.Tensor, offsets: torch.Tensor, params=None, bufs=N
     ts = _tracks_struct(bufs["tracks"])
     ss = _states_struct(bufs["states"])
     ws = bufs["ws"]
-    _check(lib().velo_reconstruct(_ptr(pixels), _ptr(offsets), E, N, C.byref(params), C.byref(hs),
+    _check(lib().velo_reconstruct(_ptr(pixels), _ptr(offsets), E, N, _geom(), C.byref(params), C.byref(hs),
                                   C.byref(ts), C.byref(ss), _ptr(ws), ws.numel(), _stream(stream)))
+    return bufs
+
+
+# ---------------------------------------------------------------------------
+# primary vertices
+
+MAX_PVS = 64
+EV_PV_OVERFLOW = 64
+
+
+class PvParams(C.Structure):
+    _fields_ = [("z0", C.c_float), ("bin_w", C.c_float), ("n_bins", C.c_int32), ("max_var", C.c_float),
+                ("seed_min", C.c_int32), ("nms", C.c_int32), ("chi2_cut", C.c_float),
+                ("n_iter", C.c_int32), ("min_weight", C.c_float)]
+
+
+class _Pvs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("n_pv", "z", "var", "weight", "status")]
+
+
+def default_pv_params(**overrides) -> PvParams:
+    p = PvParams()
+    lib().velo_pv_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def alloc_pvs(n_events: int, device="cuda") -> dict:
+    E = max(int(n_events), 1)
+    f = lambda n, dt=torch.float32: torch.empty(n, dtype=dt, device=device)  # noqa: E731
+    return dict(n_pv=f(E, torch.int32), z=f(E * MAX_PVS), var=f(E * MAX_PVS), weight=f(E * MAX_PVS),
+                status=f(E, torch.int32))
+
+
+def find_pvs(tracks: dict, states: dict, offsets, n_pixels: int, params=None, out=None, stream=None):
+    """velo_find_pvs: primary vertices from the fitted states of the tracks."""
+    E = offsets.numel() - 1
+    params = params if params is not None else default_pv_params()
+    out = out if out is not None else alloc_pvs(E, offsets.device)
+    ts, ss = _tracks_struct(tracks), _states_struct(states)
+    ps = _Pvs(*[_ptr(out[k]) for k, _ in _Pvs._fields_])
+    _check(lib().velo_find_pvs(C.byref(ts), C.byref(ss), _ptr(offsets), E, int(n_pixels), C.byref(params),
+                               C.byref(ps), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# streaming form: host memory in, compact tracks and vertices out
+
+EV_GEC = 128
+TRACK_ROW = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("tx", "<f4"), ("ty", "<f4"),
+                      ("chi2", "<f4"), ("ndof", "<i4"), ("accepted", "u1"), ("nhits", "u1"),
+                      ("pad", "<u2")])
+
+
+class _PipelineConfig(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("events_per_batch", C.c_uint32),
+                ("words_per_batch", C.c_uint64), ("gec_max_words", C.c_uint32)]
+
+
+class _PipelineResult(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("n_tracks", C.c_void_p), ("first_track", C.c_void_p),
+                ("tracks", C.c_void_p), ("track_capacity", C.c_uint64), ("n_pv", C.c_void_p),
+                ("pv_z", C.c_void_p), ("pv_var", C.c_void_p)]
+
+
+class Pipeline:
+    """velo_pipeline: host-thread / stream pairs with pinned staging; raw
+    events from host memory, compact tracks and vertices back to the host."""
+
+    def __init__(self, n_streams: int, events_per_batch: int, words_per_batch: int, gec_max_words: int = 0,
+                 params=None, mlp: "Mlp | None" = None, pv_params=None):
+        self._h = C.c_void_p()
+        cfg = _PipelineConfig(int(n_streams), int(events_per_batch), int(words_per_batch), int(gec_max_words))
+        params = params if params is not None else default_params()
+        self._keep = mlp  # the classifier's device tensors must outlive the pipeline
+        ms = mlp.struct() if mlp is not None else None
+        _check(lib().velo_pipeline_create(C.byref(self._h), C.byref(cfg), _geom(), C.byref(params),
+                                          C.byref(ms) if ms is not None else None,
+                                          C.byref(pv_params) if pv_params is not None else None))
+
+    def close(self):
+        if self._h:
+            lib().velo_pipeline_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, pixels: np.ndarray, offsets: np.ndarray, with_pvs: bool = True) -> dict:
+        px = np.ascontiguousarray(pixels, np.uint32)
+        off = np.ascontiguousarray(offsets, np.uint64)
+        E = len(off) - 1
+        cap = max(len(px) // 3, 1)
+        out = dict(status=np.zeros(E, np.uint32), n_tracks=np.zeros(E, np.uint32),
+                   first_track=np.zeros(E, np.uint64), tracks=np.zeros(cap, TRACK_ROW))
+        if with_pvs:
+            out.update(n_pv=np.zeros(E, np.uint32), pv_z=np.zeros((E, MAX_PVS), np.float32),
+                       pv_var=np.zeros((E, MAX_PVS), np.float32))
+        a = lambda k: C.c_void_p(out[k].ctypes.data) if k in out else C.c_void_p(0)  # noqa: E731
+        res = _PipelineResult(a("status"), a("n_tracks"), a("first_track"), a("tracks"), cap, a("n_pv"),
+                              a("pv_z"), a("pv_var"))
+        rows = C.c_uint64(0)
+        _check(lib().velo_pipeline_run(self._h, C.c_void_p(px.ctypes.data), len(px),
+                                       C.c_void_p(off.ctypes.data), E, C.byref(res), C.byref(rows)))
+        out["tracks"] = out["tracks"][:rows.value]
+        return out
+
+
+class KernelTimer:
+    """HIP events (created through the HIP runtime) around the main kernel of
+    each stage of velo_reconstruct_timed; durations in milliseconds."""
+    STAGES = ("cluster", "find_tracks", "fit")
+
+    def __init__(self):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = (C.c_void_p * 6)()
+        for i in range(6):
+            if self.hip.hipEventCreate(C.byref(self.ev, i * C.sizeof(C.c_void_p))) != 0:
+                raise VeloError("hipEventCreate failed")
+
+    def durations(self) -> list:
+        if self.hip.hipEventSynchronize(self.ev[5]) != 0:
+            raise VeloError("hipEventSynchronize failed")
+        out = []
+        for k in range(3):
+            ms = C.c_float(0)
+            if self.hip.hipEventElapsedTime(C.byref(ms), self.ev[2 * k], self.ev[2 * k + 1]) != 0:
+                raise VeloError("hipEventElapsedTime failed")
+            out.append(ms.value)
+        return out
+
+    def close(self):
+        for i in range(6):
+            if self.ev[i]:
+                self.hip.hipEventDestroy(self.ev[i])
+                self.ev[i] = None
+
+
+def reconstruct_timed(pixels, offsets, timer: KernelTimer, params=None, bufs=None, stream=None) -> dict:
+    """velo_reconstruct_timed: velo_reconstruct with the timer's events around
+    the main kernel of each stage (read them with timer.durations())."""
+    E = offsets.numel() - 1
+    N = _n_pixels(pixels)
+    dev = pixels.device
+    params = params if params is not None else default_params()
+    if bufs is None:
+        bufs = dict(hits=alloc_hits(N, E, dev), tracks=alloc_tracks(N, E, dev),
+                    states=alloc_states(N, dev), ws=alloc_workspace(N, E, dev))
+    hs, ts, ss = _hits_struct(bufs["hits"]), _tracks_struct(bufs["tracks"]), _states_struct(bufs["states"])
+    ws = bufs["ws"]
+    _check(lib().velo_reconstruct_timed(_ptr(pixels), _ptr(offsets), E, N, _geom(), C.byref(params), C.byref(hs),
+                                        C.byref(ts), C.byref(ss), _ptr(ws), ws.numel(), _stream(stream),
+                                        timer.ev))
     return bufs
 
 
@@ -273,7 +484,7 @@ def fit_mlp(hits, tracks, offsets, n_pixels, mlp: Mlp, params=None, states=None,
     params = params if params is not None else default_params()
     states = states if states is not None else alloc_states(n_pixels, offsets.device)
     hs, ts, ss, ms = _hits_struct(hits), _tracks_struct(tracks), _states_struct(states), mlp.struct()
-    _check(lib().velo_fit_mlp(C.byref(hs), C.byref(ts), _ptr(offsets), E, int(n_pixels),
+    _check(lib().velo_fit_mlp(C.byref(hs), C.byref(ts), _ptr(offsets), E, int(n_pixels), _geom(),
                               C.byref(params), C.byref(ms), C.byref(ss), _stream(stream)))
     return states
 
@@ -289,7 +500,7 @@ def reconstruct_mlp(pixels, offsets, mlp: Mlp, params=None, bufs=None, stream=No
     hs, ts, ss = _hits_struct(bufs["hits"]), _tracks_struct(bufs["tracks"]), _states_struct(bufs["states"])
     ms = mlp.struct()
     ws = bufs["ws"]
-    _check(lib().velo_reconstruct_mlp(_ptr(pixels), _ptr(offsets), E, N, C.byref(params), C.byref(ms),
+    _check(lib().velo_reconstruct_mlp(_ptr(pixels), _ptr(offsets), E, N, _geom(), C.byref(params), C.byref(ms),
                                       C.byref(hs), C.byref(ts), C.byref(ss), _ptr(ws), ws.numel(),
                                       _stream(stream)))
     return bufs
@@ -303,7 +514,7 @@ def track_features(hits, tracks, states, offsets, n_pixels, out=None, stream=Non
                                                   device=offsets.device)
     hs, ts, ss = _hits_struct(hits), _tracks_struct(tracks), _states_struct(states)
     _check(lib().velo_track_features(C.byref(hs), C.byref(ts), C.byref(ss), _ptr(offsets), E,
-                                     int(n_pixels), _ptr(out), _stream(stream)))
+                                     int(n_pixels), _geom(), _ptr(out), _stream(stream)))
     return out
 
 
@@ -353,9 +564,10 @@ class Context:
     """velo_context: autotuned launch shapes and the captured HIP graph of the
     batched form (persistent work-stealing kernels)."""
 
-    def __init__(self):
+    def __init__(self, params=None, geometry=None):
         self._h = C.c_void_p()
-        _check(lib().velo_context_create(C.byref(self._h)))
+        self._params = params if params is not None else default_params()
+        _check(lib().velo_context_create(C.byref(self._h), _geom(geometry), C.byref(self._params)))
 
     def close(self):
         if self._h:
@@ -368,13 +580,36 @@ class Context:
         except Exception:
             pass
 
+    SOURCES = {0: "untuned", 1: "tuned", 2: "tune cache", 3: "set"}
+
     def config(self) -> dict:
         out = (C.c_int32 * 6)()
         ms = (C.c_float * 5)()
         _check(lib().velo_context_config(self._h, out, ms))
-        return dict(tuned=bool(out[0]), cluster_grid=out[1], mid_grid=out[2], find_threads=out[3],
+        return dict(tuned=bool(out[0]), source=self.SOURCES.get(out[0], str(out[0])),
+                    cluster_grid=out[1], mid_grid=out[2], find_threads=out[3],
                     find_grid=out[4], fit_threads=out[5], tuned_ms=[float(v) for v in ms[:3]],
                     per_item_ms=[float(ms[3]), float(ms[4])])
+
+    def set_config(self, cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128):
+        """velo_context_set_config: fixed launch shapes instead of tuning."""
+        v = (C.c_int32 * 5)(cluster_grid, mid_grid, find_threads, find_grid, fit_threads)
+        _check(lib().velo_context_set_config(self._h, v))
+
+    def mlp_load(self, blob: bytes):
+        """velo_mlp_load: the context's own classifier from a blob (mlp_blob)."""
+        b = C.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().velo_mlp_load(self._h, b, len(blob)))
+
+    def mlp_save(self) -> bytes:
+        b = C.create_string_buffer(MLP_BLOB_BYTES)
+        _check(lib().velo_mlp_save(self._h, b, MLP_BLOB_BYTES))
+        return b.raw
+
+    def mlp_train_step(self, feat, label, n: int, lr: float, step: int, idx=None, loss=None, stream=None):
+        """velo_mlp_train_step: one forward / backward pass and Adam update."""
+        _check(lib().velo_mlp_train_step(self._h, _ptr(feat), _ptr(label), _ptr(idx), int(n), C.c_float(lr),
+                                         int(step), _ptr(loss), _stream(stream)))
 
     def reconstruct(self, pixels, offsets, params=None, mlp: Mlp | None = None, bufs=None, stream=None):
         E = offsets.numel() - 1
@@ -392,6 +627,37 @@ class Context:
                                               C.byref(ts), C.byref(ss), _ptr(ws), ws.numel(),
                                               _stream(stream)))
         return bufs
+
+
+MLP_BLOB_MAGIC = 0x504C4D56
+MLP_BLOB_BYTES = 16 + 4 * (N_PARAMS + 2 * N_FEATURES + 1)
+
+
+def mlp_blob(params, mean, std, threshold: float) -> bytes:
+    """The classifier blob of velo_mlp_load from host arrays (float32)."""
+    head = np.array([MLP_BLOB_MAGIC, 1, N_PARAMS, N_FEATURES], np.uint32).tobytes()
+    body = np.concatenate([np.asarray(params, np.float32).ravel(), np.asarray(mean, np.float32).ravel(),
+                           np.asarray(std, np.float32).ravel(), np.array([threshold], np.float32)])
+    assert body.size == N_PARAMS + 2 * N_FEATURES + 1
+    return head + body.astype(np.float32).tobytes()
+
+
+def parse_mlp_blob(blob: bytes):
+    """(params, mean, std, threshold) of a blob."""
+    v = np.frombuffer(blob, np.float32, offset=16)
+    return v[:N_PARAMS].copy(), v[N_PARAMS:N_PARAMS + 8].copy(), v[N_PARAMS + 8:N_PARAMS + 16].copy(), float(v[-1])
+
+
+def check_status(status_a, status_b=None, n_events=None, stream=None):
+    """velo_check_status: (0 or VELO_ERR_INPUT, OR of the status words)."""
+    t = status_a if status_a is not None else status_b
+    n = t.numel() if n_events is None else n_events
+    word = torch.empty(1, dtype=torch.int32, device=t.device)
+    h = C.c_uint32(0)
+    rc = lib().velo_check_status(_ptr(status_a), _ptr(status_b), int(n), _ptr(word), C.byref(h), _stream(stream))
+    if rc not in (0, 2):
+        _check(rc)
+    return rc, h.value
 
 
 def batched_workspace_bytes(n_pixels: int, n_events: int) -> int:

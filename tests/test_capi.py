@@ -36,11 +36,13 @@ def test_host_argument_checks():
     p = velo.default_params()
     assert abs(p.pt0_mev - 400.0) < 1e-6 and p.max_skip == 1
     # zero events: nothing to do
-    assert L.velo_cluster(None, None, 0, 0, None, None, 0, None) == 0
+    g = velo.default_geometry()
+    G = C.byref(g)
+    assert L.velo_cluster(None, None, 0, 0, G, None, None, 0, None) == 0
     # null buffers are rejected before anything is enqueued
-    assert L.velo_cluster(None, None, 3, 10, None, None, 0, None) == 1
-    assert L.velo_find_tracks(None, None, 3, 10, C.byref(p), None, None, 0, None) == 1
-    assert L.velo_fit(None, None, None, 3, 10, C.byref(p), None, None) == 1
+    assert L.velo_cluster(None, None, 3, 10, G, None, None, 0, None) == 1
+    assert L.velo_find_tracks(None, None, 3, 10, G, C.byref(p), None, None, 0, None) == 1
+    assert L.velo_fit(None, None, None, 3, 10, G, C.byref(p), None, None) == 1
     assert L.velo_status_string(1) == b"invalid argument"
     assert L.velo_workspace_bytes(1000, 10) >= L.velo_workspace_bytes(10, 10) > 0
 
@@ -50,5 +52,82 @@ def test_workspace_too_small_is_reported():
     L = velo.lib()
     fake = C.c_void_p(0x1000)
     hits = velo.velo._Hits(*[fake] * 8)
-    rc = L.velo_cluster(fake, fake, 2, 100, C.byref(hits), fake, 16, None)
+    rc = L.velo_cluster(fake, fake, 2, 100, C.byref(velo.default_geometry()), C.byref(hits), fake, 16, None)
     assert rc == 3
+
+
+
+def test_mlp_blob_is_checked_before_any_device_use():
+    """velo_mlp_load rejects a blob of the wrong size, magic, version, shape,
+    a non-finite value or a non-positive standard deviation, leaving the
+    context without a classifier (no device call is made)."""
+    import numpy as np
+
+    import paper_1912_09161_amd as velo
+    L = velo.lib()
+    ctx = velo.Context()
+    good = velo.mlp_blob(np.zeros(1377), np.zeros(8), np.ones(8), 0.5)
+    assert len(good) == velo.velo.MLP_BLOB_BYTES
+    p, m, s, t = velo.parse_mlp_blob(good)
+    assert t == 0.5 and (s == 1).all()
+    bad = [good[:-4], b"XXXX" + good[4:],
+           good[:4] + np.uint32(2).tobytes() + good[8:],
+           good[:8] + np.uint32(1376).tobytes() + good[12:],
+           velo.mlp_blob(np.full(1377, np.nan), np.zeros(8), np.ones(8), 0.5),
+           velo.mlp_blob(np.zeros(1377), np.zeros(8), np.zeros(8), 0.5),
+           velo.mlp_blob(np.zeros(1377), np.zeros(8), np.ones(8), np.inf)]
+    for b in bad:
+        buf = C.create_string_buffer(b, len(b))
+        assert L.velo_mlp_load(ctx._h, buf, len(b)) == 1
+    out = C.create_string_buffer(len(good))
+    assert L.velo_mlp_save(ctx._h, out, len(good)) == 1  # nothing loaded
+    assert L.velo_mlp_train_step(ctx._h, None, None, None, 10, C.c_float(1e-3), 1, None, None) == 1
+    ctx.close()
+
+
+def test_check_status_arguments():
+    import paper_1912_09161_amd as velo
+    L = velo.lib()
+    h = C.c_uint32(7)
+    assert L.velo_check_status(None, None, 5, C.c_void_p(0x1000), C.byref(h), None) == 1
+    assert L.velo_check_status(C.c_void_p(0x1000), None, 0, C.c_void_p(0x1000), C.byref(h), None) == 0
+    assert h.value == 0
+    assert L.velo_status_string(2) == b"at least one event is flagged"
+
+
+def test_geometry_is_checked():
+    """The built-in detector model is accepted; any other statement of it (a
+    plane moved by one ulp, another pitch, sensor size or hole, a missing
+    geometry) is rejected before anything is enqueued, by every call that
+    takes one."""
+    import numpy as np
+
+    import paper_1912_09161_amd as velo
+    L = velo.lib()
+    g = velo.default_geometry()
+    assert g.n_layers == 26 and g.n_cols == 1536 and abs(g.pitch_mm - 0.055) < 1e-7
+    assert g.z_mm[0] == np.float32(-280.0) and g.z_mm[25] == np.float32(750.0)
+    assert g.z_mm[1] == np.float32(-280.0 + 1030.0 / 25.0)
+    fake = C.c_void_p(0x1000)
+    hits = velo.velo._Hits(*[fake] * 8)
+    p = velo.default_params()
+    ok = L.velo_cluster(fake, fake, 2, 100, C.byref(g), C.byref(hits), fake, 16, None)
+    assert ok == 3  # passes the geometry check, fails on the workspace size
+
+    def variants():
+        for f, v in (("pitch_mm", 0.05), ("n_cols", 1024), ("n_rows", 1535), ("hole_r_mm", 5.0),
+                     ("n_layers", 25)):
+            b = velo.default_geometry()
+            setattr(b, f, v)
+            yield b
+        b = velo.default_geometry()
+        b.z_mm[7] = float(np.nextafter(np.float32(b.z_mm[7]), np.float32(1e9)))
+        yield b
+
+    for b in variants():
+        assert L.velo_cluster(fake, fake, 2, 100, C.byref(b), C.byref(hits), fake, 16, None) == 1
+        assert L.velo_find_tracks(C.byref(hits), fake, 2, 100, C.byref(b), C.byref(p), fake, fake, 16,
+                                  None) == 1
+        ctx = C.c_void_p()
+        assert L.velo_context_create(C.byref(ctx), C.byref(b), C.byref(p)) == 1
+    assert L.velo_cluster(fake, fake, 2, 100, None, C.byref(hits), fake, 16, None) == 1

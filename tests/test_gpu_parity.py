@@ -194,3 +194,34 @@ def test_larger_tier_capacity_edges(orc):
     g, o, _ = run_pair(orc, px, off)
     assert list(o["hits"]["layer_nhits"].reshape(-1, 26).max(1)) == [640, 641, 1024, 1025]
     assert list(g["tracks"]["n_tracks"]) == [1, 1, 1, 1] and not g["tracks"]["status"].any()
+
+
+@pytest.mark.parametrize("name", ["good", "descent", "overlap", "beyond", "empty"])
+def test_bad_offsets(orc, name):
+    """Offset tables that break the usable-offsets rule (a decreasing pair, a
+    start below an earlier offset, an end beyond the buffer) next to good
+    events: statuses equal the oracle's, flagged events have no hits and no
+    tracks, the good events' outputs equal the oracle's; plain and batched."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    from gpu_helpers import host, compare_all
+    from synth.raw import bad_offsets_case
+    b, cases = bad_offsets_case()
+    offs, exp = cases[name]
+    off = np.array(offs, np.uint64)
+    print(f"bad offsets case {name}: {offs} over {len(b.pixels)} words", flush=True)
+    g, o, _ = run_pair(orc, b.pixels, off)
+    np.testing.assert_array_equal(o["hits"]["status"], np.array(exp, np.uint32))
+    np.testing.assert_array_equal(g["hits"]["status"], np.array(exp, np.uint32))
+    px, doff = to_dev(b.pixels, off)
+    ctx = velo.Context()
+    ctx.set_config(cluster_grid=1024, mid_grid=256, find_threads=256, find_grid=512, fit_threads=128)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bufs = ctx.reconstruct(px, doff, stream=stream)
+    stream.synchronize()
+    gb = host(bufs)
+    np.testing.assert_array_equal(gb["hits"]["status"], np.array(exp, np.uint32))
+    compare_all(gb, o, off)
+    ctx.close()
