@@ -491,6 +491,25 @@ velo_status velo_pipeline_run(velo_pipeline* p, const uint32_t* h_pixels, uint64
                               const uint64_t* h_offsets, uint32_t n_events,
                               const velo_pipeline_result* out, uint64_t* n_rows);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   reconstruction as velo_reconstruct with the workspace taken from a
+   library-owned device array of VELO_NOALLOC_SCRATCH_BYTES (512 MiB), one per
+   device, set up on the first call on that device and held until the
+   process ends.  The call allocates nothing and needs no d_ws; the caller
+   still passes inputs and outputs.  A batch whose velo_workspace_bytes
+   exceeds the array returns VELO_ERR_WORKSPACE before anything is enqueued
+   (about 1600 events of the nominal occupancy fit).  Every call on one device
+   shares that device's array: calls that overlap in time on one device (on
+   different streams, or from different host threads) race and must be
+   serialised by the caller.  The kernels clear what must start at zero. */
+#define VELO_NOALLOC_SCRATCH_BYTES (512ull << 20)
+velo_status velo_reconstruct_noalloc(const uint32_t* d_pixels, const uint64_t* d_offsets,
+                                     uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                                     const velo_params* params,
+                                     const velo_hits* hits, const velo_tracks* tracks,
+                                     const velo_states* states, hipStream_t stream);
+
 const char* velo_status_string(velo_status s);
 
 #ifdef __cplusplus

@@ -117,6 +117,31 @@ void tune_store(const TuneKey& k, const velo::BatchedCfg& cfg, const float* ms) 
   memcpy(e.ms, ms, sizeof(e.ms));
 }
 
+// Scratch of velo_reconstruct_noalloc: the workspace of velo_reconstruct in
+// a file-scope device array, so that the call allocates nothing.  Each device
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name is only a stand-in: the device address of each
+// device's copy comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[VELO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch copy (nullptr on error).
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -573,6 +598,28 @@ velo_status velo_find_pvs(const velo_tracks* tracks, const velo_states* states,
       !isfinite(p->chi2_cut) || p->n_iter < 0 || p->n_iter > 64 || !isfinite(p->min_weight))
     return VELO_ERR_ARG;
   return hip_status(velo::launch_find_pvs(tracks, states, d_offsets, n_events, n_pixels, p, out, stream));
+}
+
+velo_status velo_reconstruct_noalloc(const uint32_t* d_pixels, const uint64_t* d_offsets,
+                                     uint32_t n_events, uint64_t n_pixels, const velo_geometry* geom,
+                                     const velo_params* params, const velo_hits* hits,
+                                     const velo_tracks* tracks, const velo_states* states,
+                                     hipStream_t stream) {
+  if (!geometry_ok(geom)) return VELO_ERR_ARG;
+  if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
+  if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(states) ||
+      !params_ok(params) || (n_pixels > 0 && !d_pixels))
+    return VELO_ERR_ARG;
+  if (n_pixels >= (1ull << 32) * 3) return VELO_ERR_ARG;
+  const size_t need = velo_workspace_bytes(n_pixels, n_events);
+  if (need > (size_t)VELO_NOALLOC_SCRATCH_BYTES) return VELO_ERR_WORKSPACE;
+  void* ws = scratch_address();
+  if (!ws) return VELO_ERR_HIP;
+  // every counter and list the kernels use is cleared by the kernels
+  // themselves (no memset node, no allocation)
+  return velo_reconstruct(d_pixels, d_offsets, n_events, n_pixels, geom, params, hits, tracks, states,
+                          ws, (size_t)VELO_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 velo_status velo_pipeline_create(velo_pipeline** out, const velo_pipeline_config* cfg,

@@ -97,6 +97,8 @@ def lib():
         L.velo_fit.restype = C.c_int
         L.velo_reconstruct.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
         L.velo_reconstruct.restype = C.c_int
+        L.velo_reconstruct_noalloc.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P]
+        L.velo_reconstruct_noalloc.restype = C.c_int
         L.velo_pv_params_default.argtypes = [P]
         L.velo_pv_params_default.restype = None
         L.velo_find_pvs.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P]
@@ -410,6 +412,24 @@ class Pipeline:
                                        C.c_void_p(off.ctypes.data), E, C.byref(res), C.byref(rows)))
         out["tracks"] = out["tracks"][:rows.value]
         return out
+
+
+NOALLOC_SCRATCH_BYTES = 512 << 20
+
+
+def reconstruct_noalloc(pixels, offsets, params=None, bufs=None, stream=None) -> dict:
+    """velo_reconstruct_noalloc: velo_reconstruct with the library's own device
+    scratch (no workspace argument; the library allocates nothing)."""
+    E = offsets.numel() - 1
+    N = _n_pixels(pixels)
+    dev = pixels.device
+    params = params if params is not None else default_params()
+    if bufs is None:
+        bufs = dict(hits=alloc_hits(N, E, dev), tracks=alloc_tracks(N, E, dev), states=alloc_states(N, dev))
+    hs, ts, ss = _hits_struct(bufs["hits"]), _tracks_struct(bufs["tracks"]), _states_struct(bufs["states"])
+    _check(lib().velo_reconstruct_noalloc(_ptr(pixels), _ptr(offsets), E, N, _geom(), C.byref(params), C.byref(hs),
+                                          C.byref(ts), C.byref(ss), _stream(stream)))
+    return bufs
 
 
 class KernelTimer:

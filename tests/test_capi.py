@@ -56,6 +56,26 @@ def test_workspace_too_small_is_reported():
     assert rc == 3
 
 
+def test_noalloc_rejects_batches_beyond_its_scratch():
+    """velo_reconstruct_noalloc refuses a batch whose workspace exceeds its
+    device array before touching the GPU (no HIP call is made)."""
+    import paper_1912_09161_amd as velo
+    L = velo.lib()
+    fake = C.c_void_p(0x1000)
+    p = velo.default_params()
+    hits = velo.velo._Hits(*[fake] * 8)
+    tracks = velo.velo._Tracks(*[fake] * 4)
+    states = velo.velo._States(*[fake] * 11)
+    n_px, n_ev = 10 ** 8, 20000
+    assert L.velo_workspace_bytes(n_px, n_ev) > velo.NOALLOC_SCRATCH_BYTES
+    G = C.byref(velo.default_geometry())
+    rc = L.velo_reconstruct_noalloc(fake, fake, n_ev, n_px, G, C.byref(p), C.byref(hits), C.byref(tracks),
+                                    C.byref(states), None)
+    assert rc == 3
+    assert L.velo_reconstruct_noalloc(None, None, 0, 0, G, C.byref(p), None, None, None, None) == 0
+    assert L.velo_reconstruct_noalloc(fake, None, 3, 10, G, C.byref(p), C.byref(hits), C.byref(tracks),
+                                      C.byref(states), None) == 1
+
 
 def test_mlp_blob_is_checked_before_any_device_use():
     """velo_mlp_load rejects a blob of the wrong size, magic, version, shape,
