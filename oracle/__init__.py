@@ -24,7 +24,9 @@ from .oracle import (  # noqa: F401
     find_pvs,
     find_tracks,
     fit,
+    fit_momentum,
     fit_points,
+    fit_points_p,
     layer_z,
     lib_path,
     mlp_forward,

@@ -70,6 +70,10 @@ def _L():
         lib.velo_oracle_find_tracks.argtypes = [P, P, P, P, P, P, C.c_uint32, P, P, P, P, P]
         lib.velo_oracle_fit.restype = None
         lib.velo_oracle_fit.argtypes = [P, P, P, P, C.c_uint32, P, P, P, P] + [P] * 10
+        lib.velo_oracle_fit_momentum.restype = None
+        lib.velo_oracle_fit_momentum.argtypes = [P, P, P, P, C.c_uint32, P, P, P, P, P] + [P] * 10
+        lib.velo_oracle_fit_points_p.restype = C.c_int32
+        lib.velo_oracle_fit_points_p.argtypes = [P, P, P, P, C.c_int32, C.c_float, P, P, P, P, P]
         lib.velo_oracle_fit_points.restype = C.c_int32
         lib.velo_oracle_fit_points.argtypes = [P, P, P, P, C.c_int32, P, P, P, P, P]
         lib.velo_oracle_layer_z.restype = C.c_float
@@ -173,6 +177,43 @@ def fit_into(hits, tracks, offsets, e0, e1, P, out):
                          C.byref(P), _p(out["x"]), _p(out["y"]), _p(out["z"]), _p(out["tx"]),
                          _p(out["ty"]), _p(out["cov_x"]), _p(out["cov_y"]), _p(out["chi2"]),
                          _p(out["ndof"]), _p(out["accepted"]))
+
+
+def fit_momentum(hits: dict, tracks: dict, offsets, p_mev, params=None) -> dict:
+    """The fit with a measured momentum per track slot (velo_oracle_fit_momentum)."""
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(offsets) - 1
+    cap = max(len(hits["x"]) // 3, 1)
+    pm = np.zeros(cap, np.float32)
+    pm[:len(p_mev)] = np.asarray(p_mev, np.float32)[:cap]
+    f = lambda: np.zeros(cap, np.float32)  # noqa: E731
+    out = dict(x=f(), y=f(), z=f(), tx=f(), ty=f(), cov_x=np.zeros((cap, 3), np.float32),
+               cov_y=np.zeros((cap, 3), np.float32), chi2=f(), ndof=np.zeros(cap, np.int32),
+               accepted=np.zeros(cap, np.uint8))
+    P = _params(params)
+    _L().velo_oracle_fit_momentum(_p(hits["x"]), _p(hits["y"]), _p(hits["key"]), _p(offsets), E,
+                                  _p(tracks["n_tracks"]), _p(tracks["nhits"]), _p(tracks["hit_idx"]),
+                                  _p(pm), C.byref(P), _p(out["x"]), _p(out["y"]), _p(out["z"]),
+                                  _p(out["tx"]), _p(out["ty"]), _p(out["cov_x"]), _p(out["cov_y"]),
+                                  _p(out["chi2"]), _p(out["ndof"]), _p(out["accepted"]))
+    return out
+
+
+def fit_points_p(hx, hy, hz, hlayer, p_mev, params=None):
+    """Fit one track from explicit hit coordinates with a measured momentum."""
+    hx = np.ascontiguousarray(hx, np.float32)
+    hy = np.ascontiguousarray(hy, np.float32)
+    hz = np.ascontiguousarray(hz, np.float32)
+    hl = np.ascontiguousarray(hlayer, np.int32)
+    o5 = np.zeros(5, np.float32)
+    cx = np.zeros(3, np.float32)
+    cy = np.zeros(3, np.float32)
+    chi2 = np.zeros(1, np.float32)
+    P = _params(params)
+    nd = _L().velo_oracle_fit_points_p(_p(hx), _p(hy), _p(hz), _p(hl), len(hx), C.c_float(p_mev),
+                                       C.byref(P), _p(o5), _p(cx), _p(cy), _p(chi2))
+    return dict(x=o5[0], y=o5[1], z=o5[2], tx=o5[3], ty=o5[4], cov_x=cx, cov_y=cy,
+                chi2=float(chi2[0]), ndof=int(nd))
 
 
 def fit_points(hx, hy, hz, hlayer, params=None):

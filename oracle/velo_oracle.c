@@ -442,6 +442,50 @@ static void kf_transport(okf* s, float dz)
     s->c01 = s->c01 + dz * s->c11;
 }
 
+/* the filter of both projections and the beamline transport, for a given
+   slope variance added per plane crossed (ms2) */
+static int32_t fit_points_ms2(const float* hx, const float* hy, const float* hz,
+                              const int32_t* hlayer, int32_t n, float sig2, float ms2,
+                              int through_planes,
+                              float* out5, float* cov_x, float* cov_y, float* chi2)
+{
+    okf sx = kf_project(hx, hz, hlayer, n, sig2, ms2);
+    okf sy = kf_project(hy, hz, hlayer, n, sig2, ms2);
+    float zl = hz[n - 1];
+    float num = sx.u * sx.t + sy.u * sy.t;
+    float den = sx.t * sx.t + sy.t * sy.t;
+    float dzb = den < 1e-12f ? 0.0f : -(num / den);
+    /* the particle scattered in the plane of the last hit before reaching it
+       from the beamline side: one plane of slope noise before the transport */
+    sx.c11 = sx.c11 + ms2;
+    sy.c11 = sy.c11 + ms2;
+    if (through_planes) {
+        /* and in every plane it crossed between the beamline point and the
+           last hit: transport plane by plane towards lower z, one plane of
+           slope noise at each, then the rest of the way */
+        float zb = zl + dzb, zc = zl;
+        for (int32_t l = hlayer[n - 1] - 1; l >= 0; --l) {
+            float zp = velo_oracle_layer_z(l);
+            if (!(zp > zb)) break;
+            kf_transport(&sx, zp - zc);
+            kf_transport(&sy, zp - zc);
+            sx.c11 = sx.c11 + ms2;
+            sy.c11 = sy.c11 + ms2;
+            zc = zp;
+        }
+        kf_transport(&sx, zb - zc);
+        kf_transport(&sy, zb - zc);
+    } else {
+        kf_transport(&sx, dzb);
+        kf_transport(&sy, dzb);
+    }
+    out5[0] = sx.u; out5[1] = sy.u; out5[2] = zl + dzb; out5[3] = sx.t; out5[4] = sy.t;
+    cov_x[0] = sx.c00; cov_x[1] = sx.c01; cov_x[2] = sx.c11;
+    cov_y[0] = sy.c00; cov_y[1] = sy.c01; cov_y[2] = sy.c11;
+    *chi2 = sx.chi2 + sy.chi2;
+    return 2 * n - 4;
+}
+
 int32_t velo_oracle_fit_points(const float* hx, const float* hy, const float* hz,
                                const int32_t* hlayer, int32_t n, const vo_params* p,
                                float* out5, float* cov_x, float* cov_y, float* chi2)
@@ -453,23 +497,26 @@ int32_t velo_oracle_fit_points(const float* hx, const float* hy, const float* hz
     float t2 = tx0 * tx0 + ty0 * ty0;
     float kms = (184.96f * p->x_over_x0) / (p->pt0_mev * p->pt0_mev);
     float ms2 = (kms * t2) / (1.0f + t2);
-    okf sx = kf_project(hx, hz, hlayer, n, sig2, ms2);
-    okf sy = kf_project(hy, hz, hlayer, n, sig2, ms2);
-    float zl = hz[n - 1];
-    float num = sx.u * sx.t + sy.u * sy.t;
-    float den = sx.t * sx.t + sy.t * sy.t;
-    float dzb = den < 1e-12f ? 0.0f : -(num / den);
-    /* the particle scattered in the plane of the last hit before reaching it
-       from the beamline side: one plane of slope noise before the transport */
-    sx.c11 = sx.c11 + ms2;
-    sy.c11 = sy.c11 + ms2;
-    kf_transport(&sx, dzb);
-    kf_transport(&sy, dzb);
-    out5[0] = sx.u; out5[1] = sy.u; out5[2] = zl + dzb; out5[3] = sx.t; out5[4] = sy.t;
-    cov_x[0] = sx.c00; cov_x[1] = sx.c01; cov_x[2] = sx.c11;
-    cov_y[0] = sy.c00; cov_y[1] = sy.c01; cov_y[2] = sy.c11;
-    *chi2 = sx.chi2 + sy.chi2;
-    return 2 * n - 4;
+    return fit_points_ms2(hx, hy, hz, hlayer, n, sig2, ms2, 0, out5, cov_x, cov_y, chi2);
+}
+
+/* Velo-only filter with a measured momentum (Sec. 2.3.5: the Velo segment
+   fitted with the momentum estimated from the full track).  Reading: the
+   same filter, with the slope variance per plane crossed from the track's
+   own momentum, 13.6^2 X/X0 / p^2 (Highland without the logarithm), and the
+   transport to the beamline point taken plane by plane through the planes
+   between it and the last hit, with that noise at each (the impact
+   parameter is made there); a momentum that is not a positive finite number
+   falls back to the constant transverse-momentum fit. */
+int32_t velo_oracle_fit_points_p(const float* hx, const float* hy, const float* hz,
+                                 const int32_t* hlayer, int32_t n, float p_mev, const vo_params* p,
+                                 float* out5, float* cov_x, float* cov_y, float* chi2)
+{
+    if (!(p_mev > 0.0f && p_mev <= 3.0e38f))
+        return velo_oracle_fit_points(hx, hy, hz, hlayer, n, p, out5, cov_x, cov_y, chi2);
+    float sig2 = p->sigma_meas * p->sigma_meas;
+    float ms2 = (184.96f * p->x_over_x0) / (p_mev * p_mev);
+    return fit_points_ms2(hx, hy, hz, hlayer, n, sig2, ms2, 1, out5, cov_x, cov_y, chi2);
 }
 
 void velo_oracle_fit(const float* x, const float* y, const uint32_t* key,
@@ -478,6 +525,18 @@ void velo_oracle_fit(const float* x, const float* y, const uint32_t* key,
                      const vo_params* p,
                      float* sx, float* sy, float* sz, float* stx, float* sty,
                      float* cov_x, float* cov_y, float* chi2, int32_t* ndof, uint8_t* accepted)
+{
+    velo_oracle_fit_momentum(x, y, key, offsets, n_events, n_tracks, trk_nhits, hit_idx, NULL, p,
+                             sx, sy, sz, stx, sty, cov_x, cov_y, chi2, ndof, accepted);
+}
+
+void velo_oracle_fit_momentum(const float* x, const float* y, const uint32_t* key,
+                              const uint64_t* offsets, uint32_t n_events,
+                              const uint32_t* n_tracks, const uint8_t* trk_nhits,
+                              const uint32_t* hit_idx, const float* p_mev, const vo_params* p,
+                              float* sx, float* sy, float* sz, float* stx, float* sty,
+                              float* cov_x, float* cov_y, float* chi2, int32_t* ndof,
+                              uint8_t* accepted)
 {
     for (uint32_t e = 0; e < n_events; ++e) {
         uint64_t b = offsets[e], base = b / 3;
@@ -493,8 +552,11 @@ void velo_oracle_fit(const float* x, const float* y, const uint32_t* key,
                 hz[j] = velo_oracle_layer_z(hl[j]);
             }
             float o5[5], c;
-            int32_t nd = velo_oracle_fit_points(hx, hy, hz, hl, n, p, o5, cov_x + 3 * slot,
-                                                cov_y + 3 * slot, &c);
+            int32_t nd = p_mev
+                ? velo_oracle_fit_points_p(hx, hy, hz, hl, n, p_mev[slot], p, o5, cov_x + 3 * slot,
+                                           cov_y + 3 * slot, &c)
+                : velo_oracle_fit_points(hx, hy, hz, hl, n, p, o5, cov_x + 3 * slot,
+                                         cov_y + 3 * slot, &c);
             sx[slot] = o5[0]; sy[slot] = o5[1]; sz[slot] = o5[2];
             stx[slot] = o5[3]; sty[slot] = o5[4];
             chi2[slot] = c; ndof[slot] = nd;

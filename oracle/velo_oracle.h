@@ -111,6 +111,22 @@ void velo_oracle_fit(const float* x, const float* y, const uint32_t* key,
                      float* sx, float* sy, float* sz, float* stx, float* sty,
                      float* cov_x, float* cov_y, float* chi2, int32_t* ndof, uint8_t* accepted);
 
+/* The fit with a measured momentum per track slot (p_mev[slot], MeV): the
+   slope variance per plane crossed is 13.6^2 X/X0 / p^2, and the transport
+   to the beamline point adds that noise at every plane between it and the
+   last hit; a momentum that is not a positive finite number falls back to
+   the constant pt0 fit.  With p_mev NULL this is velo_oracle_fit. */
+void velo_oracle_fit_momentum(const float* x, const float* y, const uint32_t* key,
+                              const uint64_t* offsets, uint32_t n_events,
+                              const uint32_t* n_tracks, const uint8_t* trk_nhits,
+                              const uint32_t* hit_idx, const float* p_mev, const vo_params* p,
+                              float* sx, float* sy, float* sz, float* stx, float* sty,
+                              float* cov_x, float* cov_y, float* chi2, int32_t* ndof,
+                              uint8_t* accepted);
+int32_t velo_oracle_fit_points_p(const float* hx, const float* hy, const float* hz,
+                                 const int32_t* hlayer, int32_t n, float p_mev, const vo_params* p,
+                                 float* out5, float* cov_x, float* cov_y, float* chi2);
+
 /* Fit of one track given its hit coordinates directly (decreasing z).
    Used by the closed-form checks of the filter.  out[0..4] = x, y, z, tx, ty;
    cov_x[3], cov_y[3], *chi2, returns ndof. */

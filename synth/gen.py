@@ -77,6 +77,11 @@ class Config:
     pv_z_sigma: float = 45.0
     pv_xy_sigma: float = 0.01
     eta_range: tuple = (2.0, 5.0)
+    # momentum-dependent scattering (0: fixed kink_sigma, no momentum): every
+    # particle gets pT = 100 MeV + exponential(pt_mean) and p = pT cosh(eta);
+    # the kink per crossed plane is N(0, 13.6 MeV / p * sqrt(ms_x0)) on each slope
+    ms_x0: float = 0.0
+    pt_mean: float = 0.0
 
 
 CONFIGS = {
@@ -98,6 +103,10 @@ CONFIGS = {
     # high occupancy stress, 10k events
     "stress": Config("stress", 10_000, 5, "poisson", (20.0,), "poisson", 25, 1e-4, 0.95,
                      (1, 2, 3), 1e-4),
+    # nominal occupancy with a momentum per particle and scattering that depends on it
+    # (the fit that takes a measured momentum)
+    "momentum": Config("momentum", 1000, 6, "poisson", (7.6,), "poisson", 25, 0.0, 0.98,
+                       (1, 2, 3), 1e-5, ms_x0=5.94e-4, pt_mean=500.0),
 }
 
 
@@ -114,8 +123,8 @@ class EventBatch:
     pix_pid     int32  [N]      event-local particle id of each word (-1 = noise)
     pix_q       uint8  [N]      charge of each word (same as bits 27..30)
     part_off    uint64 [E+1]    particles of event e are rows part_off[e]:part_off[e+1]
-    part        dict of arrays  per particle: eta, phi, tx, ty, pv (event-local),
-                                pv_z, pv_x, pv_y
+    part        dict of arrays  per particle: eta, phi, tx, ty, p (MeV, 0 when the
+                                config draws no momentum), pv (event-local), pv_z, pv_x, pv_y
     pv_off      uint64 [E+1]    PVs of event e
     pv          dict            per PV: z, x, y, ntrk
     """
@@ -226,11 +235,18 @@ def _gen_chunk(cfg: Config, chunk: int, n_ev: int) -> EventBatch:
     tan_theta = np.tan(2.0 * np.arctan(np.exp(-eta)))
     tx0 = tan_theta * np.cos(phi)
     ty0 = tan_theta * np.sin(phi)
+    p_mev = np.zeros(n_t)
 
     # propagation through the planes downstream of the PV
     crossed = zl[None, :] > pv_z[t_pv][:, None]                 # [T, 26]
     first = np.argmax(crossed, axis=1)
-    if cfg.kink_sigma > 0:
+    if cfg.ms_x0 > 0:
+        pt = 100.0 + rng.exponential(cfg.pt_mean, n_t)
+        p_mev = pt * np.cosh(eta)
+        sig = 13.6 / p_mev * math.sqrt(cfg.ms_x0)
+        kx = rng.normal(0.0, 1.0, (n_t, N_LAYERS)) * sig[:, None]
+        ky = rng.normal(0.0, 1.0, (n_t, N_LAYERS)) * sig[:, None]
+    elif cfg.kink_sigma > 0:
         kx = rng.normal(0.0, cfg.kink_sigma, (n_t, N_LAYERS))
         ky = rng.normal(0.0, cfg.kink_sigma, (n_t, N_LAYERS))
     else:
@@ -348,7 +364,7 @@ def _gen_chunk(cfg: Config, chunk: int, n_ev: int) -> EventBatch:
         pix_pid=m_pid.astype(np.int32),
         pix_q=m_q.astype(np.uint8),
         part_off=t_off.astype(np.uint64),
-        part=dict(eta=eta, phi=phi, tx=tx0, ty=ty0, pv=(t_pv - pv_first[t_ev]).astype(np.int32),
+        part=dict(eta=eta, phi=phi, tx=tx0, ty=ty0, p=p_mev, pv=(t_pv - pv_first[t_ev]).astype(np.int32),
                   pv_z=pv_z[t_pv], pv_x=pv_x[t_pv], pv_y=pv_y[t_pv]),
         pv_off=pv_off,
         pv=dict(z=pv_z, x=pv_x, y=pv_y, ntrk=ntrk),
