@@ -14,7 +14,12 @@ from .oracle import (  # noqa: F401
     EV_LAYER_ORDER,
     EV_OVERFLOW,
     EV_PV_OVERFLOW,
+    EV_UT_OVERFLOW,
     MAX_PVS,
+    UT_MAX_HITS,
+    UT_REGIONS,
+    UT_SECTORS,
+    UtParams,
     PvParams,
     MAX_CANDIDATES,
     N_PARAMS,
@@ -34,4 +39,7 @@ from .oracle import (  # noqa: F401
     mlp_fwd_bwd,
     pv_params,
     reconstruct,
+    ut_params,
+    ut_strip_u,
+    ut_windows,
 )

@@ -12,7 +12,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, f) for f in ("velo_oracle.c", "velo_oracle_mlp.c", "velo_oracle_pv.c")]
+_SRCS = [os.path.join(_HERE, f) for f in ("velo_oracle.c", "velo_oracle_mlp.c", "velo_oracle_pv.c",
+                                          "velo_oracle_ut.c")]
 _LIB = os.path.join(_HERE, "libvelo_oracle.so")
 
 EV_BAD_WORD = 1
@@ -22,6 +23,10 @@ EV_HOLE = 8
 EV_OVERFLOW = 16
 EV_BAD_OFFSETS = 32
 EV_PV_OVERFLOW = 64
+EV_UT_OVERFLOW = 256
+UT_SECTORS = 14
+UT_REGIONS = 56
+UT_MAX_HITS = 8192
 MAX_CANDIDATES = 65536
 MAX_PVS = 64
 
@@ -89,6 +94,12 @@ def _L():
         lib.velo_oracle_pv_params_default.argtypes = [P]
         lib.velo_oracle_find_pvs.restype = None
         lib.velo_oracle_find_pvs.argtypes = [P, C.c_uint32] + [P] * 13
+        lib.velo_oracle_ut_params_default.restype = None
+        lib.velo_oracle_ut_params_default.argtypes = [P]
+        lib.velo_oracle_ut_strip_u.restype = C.c_float
+        lib.velo_oracle_ut_strip_u.argtypes = [C.c_uint32]
+        lib.velo_oracle_ut.restype = None
+        lib.velo_oracle_ut.argtypes = [P, P, C.c_uint32, C.c_uint64, P, C.c_uint64] + [P] * 12
         lib.velo_oracle_mlp_forward_bf16.restype = None
         lib.velo_oracle_mlp_forward_bf16.argtypes = [P, P, P, P, C.c_int64, P]
         _lib = lib
@@ -358,4 +369,46 @@ def find_pvs(states: dict, tracks: dict, offsets, params: PvParams | None = None
     _L().velo_oracle_find_pvs(_p(offsets), E, _p(nt), _p(z), _p(tx), _p(ty), _p(cx), _p(cy), _p(acc),
                               C.byref(P), _p(out["n_pv"]), _p(out["z"]), _p(out["var"]),
                               _p(out["weight"]), _p(out["status"]))
+    return out
+
+
+class UtParams(C.Structure):
+    _fields_ = [("p_min_mev", C.c_float), ("kick_mev", C.c_float), ("z_kick", C.c_float),
+                ("tol_u", C.c_float), ("tol_y", C.c_float)]
+
+
+def ut_params(**overrides) -> UtParams:
+    p = UtParams()
+    _L().velo_oracle_ut_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def ut_strip_u(strip: int) -> float:
+    """u of a strip's centre (binary32), mm."""
+    return float(_L().velo_oracle_ut_strip_u(int(strip)))
+
+
+def ut_windows(ut_words, ut_offsets, offsets, tracks: dict, states: dict, params: UtParams | None = None,
+               n_pixels: int | None = None) -> dict:
+    """UT hits sorted into regions and the windows of every track slot
+    (velo_oracle_ut): sorted[M], region[E, 57], status[E], win[cap, 8].
+    n_pixels defaults to offsets[-1]."""
+    w = np.ascontiguousarray(ut_words, np.uint32)
+    uo = np.ascontiguousarray(ut_offsets, np.uint64)
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    E = len(uo) - 1
+    P = params if params is not None else ut_params()
+    f32 = lambda k: np.ascontiguousarray(states[k], np.float32).ravel()  # noqa: E731
+    nt = np.ascontiguousarray(tracks["n_tracks"], np.uint32)
+    acc = np.ascontiguousarray(states["accepted"], np.uint8)
+    cap = len(acc)
+    out = dict(sorted=np.zeros(max(len(w), 1), np.uint32), region=np.zeros((E, 57), np.uint32),
+               status=np.zeros(E, np.uint32), win=np.zeros((cap, 8), np.uint32))
+    x, y, z, tx, ty = f32("x"), f32("y"), f32("z"), f32("tx"), f32("ty")
+    npx = int(offsets[-1]) if n_pixels is None else int(n_pixels)
+    _L().velo_oracle_ut(_p(w), _p(uo), E, len(w), _p(offsets), npx, _p(nt), _p(x), _p(y), _p(z), _p(tx), _p(ty),
+                        _p(acc), C.byref(P), _p(out["sorted"]), _p(out["region"]), _p(out["status"]),
+                        _p(out["win"]))
     return out

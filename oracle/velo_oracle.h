@@ -22,6 +22,9 @@
  *                            tracks' beamline z and a weighted fit of every
  *                            candidate with every track (Sec. 2.3.1, last
  *                            paragraph)
+ *   velo_oracle_fit_momentum the fit with a measured momentum (Sec. 2.3.5)
+ *   velo_oracle_ut           UT hits sorted into regions and the search
+ *                            windows of every Velo track (Sec. 2.3.2)
  *
  * Every rule the paper leaves open (raw format, connectivity, cuts, tie
  * breaks, filter initialisation) is a written reading of the paper, stated
@@ -164,6 +167,34 @@ void velo_oracle_find_pvs(const uint64_t* offsets, uint32_t n_events, const uint
                           const float* cov_x, const float* cov_y, const uint8_t* accepted,
                           const vo_pv_params* P, uint32_t* n_pv, float* pv_z, float* pv_var,
                           float* pv_w, uint32_t* pv_status);
+
+/* Velo-to-UT search windows (velo_oracle_ut.c; Sec. 2.3.2): the UT hits of
+   every event decoded and sorted into regions (plane, sensor row), then for
+   every accepted track and UT plane the hits within the largest bending of
+   a particle above p_min.  The readings are listed at the top of
+   velo_oracle_ut.c.  Per event: sorted[ut_offsets[e] + i] (the event's words
+   in ascending order), region[57 e + r] (first sorted index of region r,
+   [56] = hits), ut_status[e]; per track slot (floor(offsets[e]/3) + t, counts
+   clamped like the fit's, none when offsets[e+1] < offsets[e] or
+   offsets[e+1] > n_pixels): win[8 slot + 2 k + i] = first | count << 16.    */
+#define VO_UT_SECTORS 14
+#define VO_UT_REGIONS 56
+#define VO_UT_MAX_HITS 8192
+#define VO_EV_UT_OVERFLOW 256u  /* more than VO_UT_MAX_HITS UT words in the event */
+typedef struct {
+    float p_min_mev;  /* smallest momentum the window admits */
+    float kick_mev;   /* transverse-momentum kick of the field between the Velo and the UT */
+    float z_kick;     /* mm, z of that kick */
+    float tol_u;      /* mm, added to the half width along u */
+    float tol_y;      /* mm, margin of the sensor rows in y */
+} vo_ut_params;
+void velo_oracle_ut_params_default(vo_ut_params* p);
+float velo_oracle_ut_strip_u(uint32_t strip);
+void velo_oracle_ut(const uint32_t* ut_words, const uint64_t* ut_offsets, uint32_t n_events,
+                    uint64_t n_ut, const uint64_t* offsets, uint64_t n_pixels, const uint32_t* n_tracks,
+                    const float* sx, const float* sy, const float* sz, const float* stx,
+                    const float* sty, const uint8_t* accepted, const vo_ut_params* P,
+                    uint32_t* sorted, uint32_t* region, uint32_t* ut_status, uint32_t* win);
 
 /* Learned track-quality classifier (velo_oracle_mlp.c): 8 features,
    8-32-32-1 network, 1377 parameters W1[32][8], b1[32], W2[32][32], b2[32],

@@ -20,6 +20,23 @@ bits [0,11) column, [11,22) row, [22,27) layer, [27,31) charge, bit 31 = 0.
 Words of one event are grouped by ascending layer; the order inside a layer
 is a random permutation (the reconstruction must not depend on it).
 
+Optional upstream-tracker (UT) hits, for the Velo-to-UT search windows
+(Sec. 2.3.2): four planes of silicon strips behind the Velo, the outer two
+with vertical strips (x layers), the inner two tilted by +5 and -5 degrees
+around z; here at z = 2327.5, 2372.5, 2597.5, 2642.5 mm, strips of
+0.1875 mm pitch measuring u = x cos(a) + y sin(a) over u in [-768, 768) mm
+(8192 strips), each strip cut into 14 sensors of 100 mm in y from
+y = -700 mm, an inactive square |x|, |y| < 40 mm around the beam.  Particles
+continue in a straight line from their state after the last Velo plane and
+are bent in x by the field between the Velo and the UT: a single kick of
+transverse momentum 45 MeV at z = 1000 mm, so x gains
+q (45 MeV / p)(z - 1000 mm) (charge q = +-1).  One strip fires per crossing
+(the paper: most UT hits are single strips, so there is no clustering) with
+an efficiency, plus uniform noise strips; strips fired twice are one hit
+(truth = lower particle id, noise last).  Raw UT word: bits [0,13) strip,
+[13,17) sensor row (sector), [17,19) layer, the rest 0; the words of an
+event in random order.
+
 Randomness: numpy's Philox counter-based generator keyed by
 (seed, chunk index); events are produced in fixed chunks of CHUNK events, so
 the first n events of a config are the same whatever the total requested.
@@ -82,6 +99,10 @@ class Config:
     # the kink per crossed plane is N(0, 13.6 MeV / p * sqrt(ms_x0)) on each slope
     ms_x0: float = 0.0
     pt_mean: float = 0.0
+    # upstream-tracker hits (needs a momentum per particle, ms_x0 > 0)
+    ut: bool = False
+    ut_eff: float = 0.99
+    ut_noise: float = 100.0  # mean noise strips per (event, UT layer)
 
 
 CONFIGS = {
@@ -107,7 +128,23 @@ CONFIGS = {
     # (the fit that takes a measured momentum)
     "momentum": Config("momentum", 1000, 6, "poisson", (7.6,), "poisson", 25, 0.0, 0.98,
                        (1, 2, 3), 1e-5, ms_x0=5.94e-4, pt_mean=500.0),
+    # the same with upstream-tracker hits (the Velo-to-UT search windows)
+    "ut": Config("ut", 1000, 7, "poisson", (7.6,), "poisson", 25, 0.0, 0.98,
+                 (1, 2, 3), 1e-5, ms_x0=5.94e-4, pt_mean=500.0, ut=True),
 }
+
+# upstream tracker (generator's model; see the module docstring)
+UT_Z_MM = (2327.5, 2372.5, 2597.5, 2642.5)
+UT_ANGLE_DEG = (0.0, 5.0, -5.0, 0.0)
+UT_PITCH_MM = 0.1875
+UT_U0_MM = -768.0
+UT_STRIPS = 8192
+UT_Y0_MM = -700.0
+UT_SECTOR_MM = 100.0
+UT_SECTORS = 14
+UT_HOLE_MM = 40.0
+UT_KICK_MEV = 45.0
+UT_Z_KICK_MM = 1000.0
 
 
 def make_config(name: str, **overrides) -> Config:
@@ -127,6 +164,9 @@ class EventBatch:
                                 config draws no momentum), pv (event-local), pv_z, pv_x, pv_y
     pv_off      uint64 [E+1]    PVs of event e
     pv          dict            per PV: z, x, y, ntrk
+    ut_words    uint32 [M]      raw UT words (None when the config has no UT)
+    ut_offsets  uint64 [E+1]    event e owns ut_words[ut_offsets[e]:ut_offsets[e+1]]
+    ut_pid      int32  [M]      event-local particle id of each UT word (-1 = noise)
     """
     pixels: np.ndarray
     offsets: np.ndarray
@@ -136,6 +176,9 @@ class EventBatch:
     part: dict
     pv_off: np.ndarray
     pv: dict
+    ut_words: np.ndarray | None = None
+    ut_offsets: np.ndarray | None = None
+    ut_pid: np.ndarray | None = None
 
     @property
     def n_events(self) -> int:
@@ -162,6 +205,12 @@ def _slice(b: EventBatch, e0: int, e1: int) -> EventBatch:
     p0, p1 = int(b.offsets[e0]), int(b.offsets[e1])
     q0, q1 = int(b.part_off[e0]), int(b.part_off[e1])
     v0, v1 = int(b.pv_off[e0]), int(b.pv_off[e1])
+    ut = {}
+    if b.ut_words is not None:
+        u0, u1 = int(b.ut_offsets[e0]), int(b.ut_offsets[e1])
+        ut = dict(ut_words=b.ut_words[u0:u1].copy(),
+                  ut_offsets=(b.ut_offsets[e0:e1 + 1] - b.ut_offsets[e0]).astype(np.uint64),
+                  ut_pid=b.ut_pid[u0:u1].copy())
     return EventBatch(
         pixels=b.pixels[p0:p1].copy(),
         offsets=(b.offsets[e0:e1 + 1] - b.offsets[e0]).astype(np.uint64),
@@ -171,6 +220,7 @@ def _slice(b: EventBatch, e0: int, e1: int) -> EventBatch:
         part={k: v[q0:q1].copy() for k, v in b.part.items()},
         pv_off=(b.pv_off[e0:e1 + 1] - b.pv_off[e0]).astype(np.uint64),
         pv={k: v[v0:v1].copy() for k, v in b.pv.items()},
+        **ut,
     )
 
 
@@ -194,6 +244,10 @@ def concat(batches) -> EventBatch:
         part={k: np.concatenate([b.part[k] for b in batches]) for k in batches[0].part},
         pv_off=cat_off([b.pv_off for b in batches]),
         pv={k: np.concatenate([b.pv[k] for b in batches]) for k in batches[0].pv},
+        **(dict(ut_words=np.concatenate([b.ut_words for b in batches]).astype(np.uint32),
+                ut_offsets=cat_off([b.ut_offsets for b in batches]),
+                ut_pid=np.concatenate([b.ut_pid for b in batches]).astype(np.int32))
+           if batches[0].ut_words is not None else {}),
     )
 
 
@@ -358,6 +412,11 @@ def _gen_chunk(cfg: Config, chunk: int, n_ev: int) -> EventBatch:
     pv_off = np.zeros(n_ev + 1, np.uint64)
     np.cumsum(npv, out=pv_off[1:])
     pv_first = pv_off[:-1].astype(np.int64)
+    ut = {}
+    if cfg.ut:
+        # state after the last Velo plane (every particle crosses it: its PV lies upstream)
+        ut = _ut_hits(rng, cfg, n_ev, t_ev, t_off, p_mev, x[:, -1], y[:, -1], tx_after[:, -1],
+                      ty_after[:, -1], zl[-1])
     return EventBatch(
         pixels=words,
         offsets=offsets,
@@ -368,7 +427,51 @@ def _gen_chunk(cfg: Config, chunk: int, n_ev: int) -> EventBatch:
                   pv_z=pv_z[t_pv], pv_x=pv_x[t_pv], pv_y=pv_y[t_pv]),
         pv_off=pv_off,
         pv=dict(z=pv_z, x=pv_x, y=pv_y, ntrk=ntrk),
+        **ut,
     )
+
+
+def _ut_hits(rng, cfg, n_ev, t_ev, t_off, p_mev, x_end, y_end, tx_end, ty_end, z_end):
+    """Raw UT words of the chunk's particles (model in the module docstring)."""
+    n_t = len(t_ev)
+    q = np.where(rng.random(n_t) < 0.5, -1.0, 1.0)
+    words, ev, pid = [], [], []
+    for k, (zk, ang) in enumerate(zip(UT_Z_MM, UT_ANGLE_DEG)):
+        a = math.radians(ang)
+        xk = x_end + tx_end * (zk - z_end) + q * (UT_KICK_MEV / p_mev) * (zk - UT_Z_KICK_MM)
+        yk = y_end + ty_end * (zk - z_end)
+        u = xk * math.cos(a) + yk * math.sin(a)
+        strip = np.floor((u - UT_U0_MM) / UT_PITCH_MM).astype(np.int64)
+        sec = np.floor((yk - UT_Y0_MM) / UT_SECTOR_MM).astype(np.int64)
+        ok = (strip >= 0) & (strip < UT_STRIPS) & (sec >= 0) & (sec < UT_SECTORS)
+        ok &= ~((np.abs(xk) < UT_HOLE_MM) & (np.abs(yk) < UT_HOLE_MM))
+        ok &= rng.random(n_t) < cfg.ut_eff
+        idx = np.nonzero(ok)[0]
+        words.append(strip[idx] | (sec[idx] << 13) | (k << 17))
+        ev.append(t_ev[idx])
+        pid.append(idx - t_off[t_ev[idx]])
+        nn = rng.poisson(cfg.ut_noise, n_ev)
+        tot = int(nn.sum())
+        words.append(rng.integers(0, UT_STRIPS, tot) | (rng.integers(0, UT_SECTORS, tot) << 13) | (k << 17))
+        ev.append(np.repeat(np.arange(n_ev), nn))
+        pid.append(np.full(tot, -1, np.int64))
+    w = np.concatenate(words).astype(np.int64)
+    e = np.concatenate(ev).astype(np.int64)
+    pid = np.concatenate(pid).astype(np.int64)
+    # one hit per fired strip: lowest particle id wins, noise last
+    pk = np.where(pid < 0, (1 << 23) - 1, pid)
+    order = np.argsort((e << 42) | (w << 23) | pk)
+    key = (e << 19 | w)[order]
+    first = np.ones(len(key), bool)
+    first[1:] = key[1:] != key[:-1]
+    sel = order[first]
+    w, e, pid = w[sel], e[sel], pid[sel]
+    # random order inside an event
+    order = np.argsort((e << 32) | rng.integers(0, 1 << 32, len(e), dtype=np.int64))
+    w, e, pid = w[order], e[order], pid[order]
+    off = np.zeros(n_ev + 1, np.uint64)
+    np.cumsum(np.bincount(e, minlength=n_ev), out=off[1:])
+    return dict(ut_words=w.astype(np.uint32), ut_offsets=off, ut_pid=pid.astype(np.int32))
 
 
 def _chunk_part(args):
