@@ -218,6 +218,24 @@ velo_status velo_fit(const velo_hits* hits, const velo_tracks* tracks, const uin
                      const velo_params* params,
                      const velo_states* out, hipStream_t stream);
 
+/* The fit with a measured momentum (paper Sec. 2.3.5: the Velo-only Kalman
+   filter is run again with the momentum estimated from the whole track,
+   which improves the impact-parameter resolution).  d_p_mev[slot] (device,
+   capacity floor(n_pixels/3) slots) is the momentum of the track in that
+   slot in MeV.  The filter is velo_fit's with the slope variance added per
+   plane crossed = 13.6^2 X/X0 / p^2 (Highland without its logarithm), and
+   the transport from the last hit to the beamline point of closest approach
+   is taken plane by plane through the planes in between, adding that
+   variance at each (the particle crosses them before it reaches the last
+   hit).  A momentum that is not a positive finite number gives velo_fit's
+   result for that track.  accepted: the plain cut; score (may be NULL):
+   chi2/ndof.  Track counts are checked as in velo_fit.  d_p_mev NULL:
+   VELO_ERR_ARG.                                                            */
+velo_status velo_fit_momentum(const velo_hits* hits, const velo_tracks* tracks,
+                              const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
+                              const velo_geometry* geom, const velo_params* params,
+                              const float* d_p_mev, const velo_states* out, hipStream_t stream);
+
 /* velo_cluster, velo_find_tracks and velo_fit enqueued back to back. */
 velo_status velo_reconstruct(const uint32_t* d_pixels, const uint64_t* d_offsets, uint32_t n_events,
                              uint64_t n_pixels, const velo_geometry* geom, const velo_params* params, const velo_hits* hits,
@@ -426,6 +444,67 @@ typedef struct {
 velo_status velo_find_pvs(const velo_tracks* tracks, const velo_states* states,
                           const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
                           const velo_pv_params* params, const velo_pvs* out, hipStream_t stream);
+
+/* Velo-to-UT search windows (paper Sec. 2.3.2: the upstream tracker's hits
+   are decoded into regions and sorted for a fast look-up, and every Velo
+   track is extrapolated to it with the largest bending a particle above
+   3 GeV can have).  The paper gives only four strip planes, the outer two
+   with vertical strips and the inner two tilted by +5 and -5 degrees; the
+   model of this library:
+     planes    k = 0..3 at z = 2327.5, 2372.5, 2597.5, 2642.5 mm, strip angles
+               0, +5, -5, 0 degrees; a strip measures u = x c_k + y s_k with
+               (c_k, s_k) = (1, 0), (0.9961947, 0.08715574),
+               (0.9961947, -0.08715574), (1, 0) in binary32;
+     strips    8192 of 0.1875 mm: strip n has u = ((float)n + 0.5) 0.1875 - 768;
+               each cut into 14 sensor rows of 100 mm, row j covering y in
+               [-700 + 100 j, -600 + 100 j);
+     raw word  bits [0,13) strip, [13,17) sensor row (< 14), [17,19) plane,
+               the rest 0; any order inside an event;
+     regions   region r = 14 k + j; an event's words sorted ascending (plane,
+               row, strip) make every region a run sorted along u.
+   Per event e (UT words [ut_offsets[e], ut_offsets[e+1]), same usable-offsets
+   rule as the pixel offsets, at most VELO_UT_MAX_HITS):
+     sorted[ut_offsets[e] + i]  the event's words in ascending order (written
+                                only for events whose UT status is 0)
+     region[57 e + r]           index (event-relative) of the first word of
+                                region r, [56] = words; zeros for a flagged event
+     status[e]                  VELO_EV_BAD_OFFSETS (UT offsets), UT_OVERFLOW,
+                                BAD_WORD, or DUPLICATE (only when no other bit)
+   Per track slot s = floor(offsets[e]/3) + t, t < n_tracks[e] (clamped like
+   velo_fit's, none when offsets[e+1] < offsets[e] or > n_pixels), 8 words
+   win[8 s + 2 k + i] = first | count << 16: the hits of plane k in the i-th
+   sensor row the track may cross (rows j with yp + tol_y >= y_lo(j) and
+   yp - tol_y < y_hi(j), at most two, increasing j), first = event-relative
+   index in `sorted`, count = hits with up - w_k <= u <= up + w_k, 0 if none,
+   where from the beamline state dz = z_k - z, xp = x + tx dz, yp = y + ty dz,
+   up = xp c_k + yp s_k and w_k = ((kick / p_min) (z_k - z_kick)) c_k + tol_u
+   (the largest x bending of a particle above p_min for one transverse kick at
+   z_kick).  Tracks not accepted, or of a flagged event, get zeros.  win must
+   be 16-byte aligned.  One workgroup per event, no workspace.              */
+#define VELO_UT_MAX_HITS 8192u
+#define VELO_UT_REGIONS 56
+#define VELO_EV_UT_OVERFLOW 256u  /* more than VELO_UT_MAX_HITS UT words in the event */
+typedef struct {
+    float p_min_mev;  /* smallest momentum the window admits (3000) */
+    float kick_mev;   /* transverse-momentum kick between Velo and UT (45) */
+    float z_kick;     /* mm, z of that kick (1000) */
+    float tol_u;      /* mm, added to the half width along u (1) */
+    float tol_y;      /* mm, margin of the sensor rows in y (10) */
+} velo_ut_params;
+void velo_ut_params_default(velo_ut_params* p);
+typedef struct {
+    uint32_t* sorted;  /* [n_ut] */
+    uint32_t* region;  /* [n_events * 57] */
+    uint32_t* status;  /* [n_events] */
+    uint32_t* win;     /* [track capacity * 8] */
+} velo_ut_out;
+/* Reads the states (x, y, z, tx, ty, accepted) of the tracks; params must be
+   finite with p_min_mev > 0.                                               */
+velo_status velo_ut_windows(const uint32_t* d_ut_words, const uint64_t* d_ut_offsets,
+                            uint32_t n_events, uint64_t n_ut, const velo_tracks* tracks,
+                            const velo_states* states, const uint64_t* d_offsets,
+                            uint64_t n_pixels, const velo_ut_params* params,
+                            const velo_ut_out* out, hipStream_t stream);
 
 /* Streaming form (paper Sec. 2.2: raw events are copied to the GPU and only
    tracks and vertices come back; Sec. 3.2: several host-thread / GPU-stream

@@ -16,6 +16,11 @@
 //        (13.6 MeV Highland constant, p = pt0 sqrt(1+t2)/sqrt(t2))
 //   beamline: dzb = -(x tx + y ty)/(tx tx + ty ty) (0 if the slope is below
 //        1e-6), one plane of slope noise, then transport by dzb.
+// With a measured momentum p per track (Sec. 2.3.5: the Velo segment fitted
+// with the momentum of the whole track) ms2 = 184.96 X/X0 / p^2, and the
+// transport to the beamline point stops at every plane between it and the
+// last hit, adding ms2 to the slope variance at each; a p that is not a
+// positive finite number falls back to the constant-pt0 fit.
 #include "velo_device.hpp"
 #include "mlp.hip"
 
@@ -24,6 +29,7 @@ namespace velo {
 struct FitConst {
   float sig2;  // sigma_meas^2
   float kms;   // 184.96 * x_over_x0 / pt0^2
+  float k184;  // 184.96 * x_over_x0
   float qc3, qc4;
 };
 
@@ -63,12 +69,14 @@ struct FitOut {
 
 // Fit the track in `slot` (hits in decreasing z).  Returns false for a
 // malformed track.  All hit indices, then all coordinates are loaded before
-// the filter runs, so a track costs two memory round trips.
+// the filter runs, so a track costs two memory round trips.  MOM: p_mev is
+// the track's measured momentum (see the file header).
+template <bool MOM = false>
 __device__ __forceinline__ bool fit_track(const float* __restrict__ X, const float* __restrict__ Y,
                                           const uint32_t* __restrict__ key, uint64_t b, uint32_t ne,
                                           const uint8_t* __restrict__ nhits,
                                           const uint32_t* __restrict__ hit_idx, uint64_t slot,
-                                          const FitConst& P, FitOut& o) {
+                                          const FitConst& P, FitOut& o, float p_mev = 0.0f) {
   const int n = nhits[slot];
   if (n < 3 || n > kLayers) return false;
   const uint32_t* hi = hit_idx + 26ull * slot;
@@ -99,7 +107,14 @@ __device__ __forceinline__ bool fit_track(const float* __restrict__ X, const flo
   const float tx0 = (xs[1] - xs[0]) / d;
   const float ty0 = (ys[1] - ys[0]) / d;
   const float t2 = tx0 * tx0 + ty0 * ty0;
-  const float ms2 = (P.kms * t2) / (1.0f + t2);
+  bool thru = false;  // transport through the planes below the last hit
+  float ms2;
+  if constexpr (MOM) {
+    thru = p_mev > 0.0f && p_mev <= 3.0e38f;
+    ms2 = thru ? P.k184 / (p_mev * p_mev) : (P.kms * t2) / (1.0f + t2);
+  } else {
+    ms2 = (P.kms * t2) / (1.0f + t2);
+  }
   const float s2 = P.sig2;
   Kf1 sx{xs[1], tx0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
   Kf1 sy{ys[1], ty0, s2, s2 / d, (2.0f * s2) / (d * d), 0.0f};
@@ -122,8 +137,25 @@ __device__ __forceinline__ bool fit_track(const float* __restrict__ X, const flo
   const float dzb = den < 1e-12f ? 0.0f : -(num / den);
   sx.c11 = sx.c11 + ms2;
   sy.c11 = sy.c11 + ms2;
-  kf_transport(sx, dzb);
-  kf_transport(sy, dzb);
+  if (MOM && thru) {
+    // plane by plane towards the beamline point, slope noise at each plane
+    const float zb = zp + dzb;
+    float zc = zp;
+    for (int l = (int)lp - 1; l >= 0; --l) {
+      const float zl = kLayerZ[l];
+      if (!(zl > zb)) break;
+      kf_transport(sx, zl - zc);
+      kf_transport(sy, zl - zc);
+      sx.c11 = sx.c11 + ms2;
+      sy.c11 = sy.c11 + ms2;
+      zc = zl;
+    }
+    kf_transport(sx, zb - zc);
+    kf_transport(sy, zb - zc);
+  } else {
+    kf_transport(sx, dzb);
+    kf_transport(sy, dzb);
+  }
   o.x = sx.u; o.y = sy.u; o.z = zp + dzb; o.tx = sx.t; o.ty = sy.t;
   o.cx[0] = sx.c00; o.cx[1] = sx.c01; o.cx[2] = sx.c11;
   o.cy[0] = sy.c00; o.cy[1] = sy.c01; o.cy[2] = sy.c11;
@@ -172,6 +204,36 @@ __global__ __launch_bounds__(NT) void k_fit(const float* __restrict__ X,
     const uint64_t slot = base + t;
     FitOut f;
     if (!fit_track(X, Y, key, b, ne, nhits, hit_idx, slot, P, f)) continue;
+    store_state(o, slot, f);
+    const float r = f.chi2 / (float)f.ndof;
+    o.accepted[slot] = (uint8_t)(f.n >= 4 ? (r <= P.qc4) : (r <= P.qc3));
+    if (o.score) o.score[slot] = r;
+  }
+}
+
+// The fit with a measured momentum per track slot (p_mev[slot], MeV), plain
+// chi2/hit-count cut.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fit_momentum(const float* __restrict__ X,
+                                                     const float* __restrict__ Y,
+                                                     const uint32_t* __restrict__ key,
+                                                     const uint64_t* __restrict__ offsets,
+                                                     uint64_t n_pixels,
+                                                     const uint32_t* __restrict__ n_tracks,
+                                                     const uint8_t* __restrict__ nhits,
+                                                     const uint32_t* __restrict__ hit_idx,
+                                                     const float* __restrict__ p_mev, FitConst P,
+                                                     velo_states o) {
+  const uint32_t e = blockIdx.x;
+  const uint64_t b = offsets[e], end = offsets[e + 1];
+  if (end < b || end > n_pixels) return;
+  const uint32_t ne = (uint32_t)(end - b);
+  const uint64_t base = b / 3;
+  const uint32_t nt = event_tracks(n_tracks[e], ne);
+  for (uint32_t t = threadIdx.x; t < nt; t += NT) {
+    const uint64_t slot = base + t;
+    FitOut f;
+    if (!fit_track<true>(X, Y, key, b, ne, nhits, hit_idx, slot, P, f, p_mev[slot])) continue;
     store_state(o, slot, f);
     const float r = f.chi2 / (float)f.ndof;
     o.accepted[slot] = (uint8_t)(f.n >= 4 ? (r <= P.qc4) : (r <= P.qc3));
@@ -231,6 +293,7 @@ FitConst make_fit_const(const velo_params* p) {
   FitConst c;
   c.sig2 = p->sigma_meas * p->sigma_meas;
   c.kms = (184.96f * p->x_over_x0) / (p->pt0_mev * p->pt0_mev);
+  c.k184 = 184.96f * p->x_over_x0;
   c.qc3 = p->qc3;
   c.qc4 = p->qc4;
   return c;
@@ -274,6 +337,15 @@ hipError_t launch_fit_mlp(const velo_hits* h, const velo_tracks* t, const uint64
                           uint32_t n_events, uint64_t n_pixels, const velo_params* p,
                           const velo_mlp* m, const velo_states* o, hipStream_t s) {
   return launch_fit_cfg(h, t, offsets, n_events, n_pixels, p, m, o, s, kFitThreads);
+}
+
+hipError_t launch_fit_momentum(const velo_hits* h, const velo_tracks* t, const uint64_t* offsets,
+                               uint32_t n_events, uint64_t n_pixels, const velo_params* p,
+                               const float* p_mev, const velo_states* o, hipStream_t s) {
+  const FitConst c = make_fit_const(p);
+  hipLaunchKernelGGL(k_fit_momentum<kFitThreads>, dim3(n_events), dim3(kFitThreads), 0, s, h->x, h->y,
+                     h->key, offsets, n_pixels, t->n_tracks, t->nhits, t->hit_idx, p_mev, c, *o);
+  return hipGetLastError();
 }
 
 }  // namespace velo

@@ -3,6 +3,7 @@
 // Built as one translation unit with the kernels it launches.
 #include "batched.hip"
 #include "pv.hip"
+#include "ut.hip"
 #include "pipeline.hip"
 
 #include <math.h>
@@ -210,6 +211,20 @@ velo_status velo_fit(const velo_hits* hits, const velo_tracks* tracks, const uin
   if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(out) || !params_ok(params))
     return VELO_ERR_ARG;
   return hip_status(velo::launch_fit(hits, tracks, d_offsets, n_events, n_pixels, params, out, stream));
+}
+
+velo_status velo_fit_momentum(const velo_hits* hits, const velo_tracks* tracks,
+                              const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,
+                              const velo_geometry* geom, const velo_params* params,
+                              const float* d_p_mev, const velo_states* out, hipStream_t stream) {
+  if (!geometry_ok(geom)) return VELO_ERR_ARG;
+  if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
+  if (!d_offsets || !hits_ok(hits) || !tracks_ok(tracks) || !states_ok(out) || !params_ok(params) ||
+      !d_p_mev)
+    return VELO_ERR_ARG;
+  return hip_status(velo::launch_fit_momentum(hits, tracks, d_offsets, n_events, n_pixels, params,
+                                              d_p_mev, out, stream));
 }
 
 velo_status velo_reconstruct(const uint32_t* d_pixels, const uint64_t* d_offsets, uint32_t n_events,
@@ -598,6 +613,34 @@ velo_status velo_find_pvs(const velo_tracks* tracks, const velo_states* states,
       !isfinite(p->chi2_cut) || p->n_iter < 0 || p->n_iter > 64 || !isfinite(p->min_weight))
     return VELO_ERR_ARG;
   return hip_status(velo::launch_find_pvs(tracks, states, d_offsets, n_events, n_pixels, p, out, stream));
+}
+
+void velo_ut_params_default(velo_ut_params* p) {
+  if (!p) return;
+  p->p_min_mev = 3000.0f;
+  p->kick_mev = 45.0f;
+  p->z_kick = 1000.0f;
+  p->tol_u = 1.0f;
+  p->tol_y = 10.0f;
+}
+
+velo_status velo_ut_windows(const uint32_t* d_ut_words, const uint64_t* d_ut_offsets,
+                            uint32_t n_events, uint64_t n_ut, const velo_tracks* tracks,
+                            const velo_states* states, const uint64_t* d_offsets,
+                            uint64_t n_pixels, const velo_ut_params* params,
+                            const velo_ut_out* out, hipStream_t stream) {
+  if (n_events == 0) return VELO_OK;
+  if (n_events > VELO_MAX_EVENTS) return VELO_ERR_ARG;
+  if (!d_ut_offsets || (n_ut > 0 && !d_ut_words) || !d_offsets || !tracks || !tracks->n_tracks ||
+      !states || !states->x || !states->y || !states->z || !states->tx || !states->ty ||
+      !states->accepted || !params || !out || !out->sorted || !out->region || !out->status ||
+      !out->win || ((uintptr_t)out->win & 15u) != 0)
+    return VELO_ERR_ARG;
+  if (!(params->p_min_mev > 0.0f) || !isfinite(params->p_min_mev) || !isfinite(params->kick_mev) ||
+      !isfinite(params->z_kick) || !isfinite(params->tol_u) || !isfinite(params->tol_y))
+    return VELO_ERR_ARG;
+  return hip_status(velo::launch_ut(d_ut_words, d_ut_offsets, n_events, n_ut, d_offsets, n_pixels, tracks,
+                                    states, params, out, stream));
 }
 
 velo_status velo_reconstruct_noalloc(const uint32_t* d_pixels, const uint64_t* d_offsets,

@@ -95,6 +95,12 @@ def lib():
         L.velo_find_tracks.restype = C.c_int
         L.velo_fit.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P]
         L.velo_fit.restype = C.c_int
+        L.velo_fit_momentum.argtypes = [P, P, P, C.c_uint32, C.c_uint64, P, P, P, P, P]
+        L.velo_fit_momentum.restype = C.c_int
+        L.velo_ut_params_default.argtypes = [P]
+        L.velo_ut_params_default.restype = None
+        L.velo_ut_windows.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, C.c_uint64, P, P, P]
+        L.velo_ut_windows.restype = C.c_int
         L.velo_reconstruct.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
         L.velo_reconstruct.restype = C.c_int
         L.velo_reconstruct_noalloc.argtypes = [P, P, C.c_uint32, C.c_uint64, P, P, P, P, P, P]
@@ -286,6 +292,21 @@ def fit(hits: dict, tracks: dict, offsets: torch.Tensor, n_pixels: int, params=N
     return states
 
 
+def fit_momentum(hits: dict, tracks: dict, offsets: torch.Tensor, n_pixels: int, p_mev: torch.Tensor,
+                 params=None, states=None, stream=None) -> dict:
+    """velo_fit_momentum: the fit with a measured momentum per track slot
+    (p_mev: float32 device tensor of at least the track capacity)."""
+    E = offsets.numel() - 1
+    if p_mev.dtype != torch.float32 or p_mev.numel() < track_capacity(n_pixels):
+        raise VeloError("p_mev must be float32 with one value per track slot")
+    params = params if params is not None else default_params()
+    states = states if states is not None else alloc_states(n_pixels, offsets.device)
+    hs, ts, ss = _hits_struct(hits), _tracks_struct(tracks), _states_struct(states)
+    _check(lib().velo_fit_momentum(C.byref(hs), C.byref(ts), _ptr(offsets), E, int(n_pixels), _geom(),
+                                   C.byref(params), _ptr(p_mev), C.byref(ss), _stream(stream)))
+    return states
+
+
 def reconstruct(pixels: torch.Tensor, offsets: torch.Tensor, params=None, bufs=None, stream=None) -> dict:
     """velo_reconstruct over a packed batch; returns dict(hits, tracks, states, ws)."""
     E = offsets.numel() - 1
@@ -345,6 +366,50 @@ def find_pvs(tracks: dict, states: dict, offsets, n_pixels: int, params=None, ou
     ps = _Pvs(*[_ptr(out[k]) for k, _ in _Pvs._fields_])
     _check(lib().velo_find_pvs(C.byref(ts), C.byref(ss), _ptr(offsets), E, int(n_pixels), C.byref(params),
                                C.byref(ps), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Velo-to-UT search windows
+
+UT_REGIONS = 56
+EV_UT_OVERFLOW = 256
+
+
+class UtParams(C.Structure):
+    _fields_ = [("p_min_mev", C.c_float), ("kick_mev", C.c_float), ("z_kick", C.c_float),
+                ("tol_u", C.c_float), ("tol_y", C.c_float)]
+
+
+class _UtOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("sorted", "region", "status", "win")]
+
+
+def default_ut_params(**overrides) -> UtParams:
+    p = UtParams()
+    lib().velo_ut_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def alloc_ut(n_ut: int, n_events: int, n_pixels: int, device="cuda") -> dict:
+    i = lambda n: torch.zeros(max(int(n), 1), dtype=torch.int32, device=device)  # noqa: E731
+    return dict(sorted=i(n_ut), region=i(n_events * (UT_REGIONS + 1)), status=i(n_events),
+                win=i(track_capacity(n_pixels) * 8))
+
+
+def ut_windows(ut_words, ut_offsets, tracks: dict, states: dict, offsets, n_pixels: int, params=None,
+               out=None, stream=None) -> dict:
+    """velo_ut_windows: UT hits sorted into regions and the search window of
+    every track slot on every UT plane."""
+    E = ut_offsets.numel() - 1
+    params = params if params is not None else default_ut_params()
+    out = out if out is not None else alloc_ut(ut_words.numel(), E, n_pixels, ut_offsets.device)
+    ts, ss = _tracks_struct(tracks), _states_struct(states)
+    us = _UtOut(*[_ptr(out[k]) for k, _ in _UtOut._fields_])
+    _check(lib().velo_ut_windows(_ptr(ut_words), _ptr(ut_offsets), E, ut_words.numel(), C.byref(ts), C.byref(ss),
+                                 _ptr(offsets), int(n_pixels), C.byref(params), C.byref(us), _stream(stream)))
     return out
 
 
