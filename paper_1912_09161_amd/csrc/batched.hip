@@ -161,6 +161,7 @@ struct BatchedCfg {
   int find_threads;
   uint32_t find_grid;    // persistent track-finding workgroups (0: one per event)
   int fit_threads;
+  uint32_t esc_grid[3];  // workgroups of the middle, large and workspace track-finding tiers
 };
 
 size_t batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
@@ -214,7 +215,8 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
   if (stages & 2) {
     if (k.find_grid)  // work-stealing counters of the persistent track-finding tiers
       hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 3u);
-    const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2};
+    const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2,
+                     {k.esc_grid[0], k.esc_grid[1], k.esc_grid[2]}};
     hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
                                    c.ws, s, fc);
     if (e != hipSuccess) return e;
@@ -245,7 +247,7 @@ struct velo_context {
   velo_params params{};  // used when a call passes no parameters
   bool tuned = false;
   int source = 0;  // how cfg was chosen: 1 tuned here, 2 tune cache, 3 set by the caller
-  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128};
+  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128, {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks}};
   float tuned_ms[5] = {0, 0, 0, 0, 0};
   // captured graphs of recent call shapes (buffers, sizes, parameters, stream)
   static constexpr int kGraphs = 32;
@@ -360,6 +362,24 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     best.find_grid = pick[p].find_grid;
     ctx->tuned_ms[1] = bt[p];
     ctx->tuned_ms[4] = bt[0];
+    // workgroups of the tiers that take the events the small tier hands on:
+    // the smallest grids within 2 % of the best time on the tuning stream
+    // (a tier's launch keeps its grid's LDS reserved until every workgroup
+    // has been placed, which delays other streams' work when only a few
+    // events escalate)
+    const uint32_t esc[3][3] = {{kMBlocks, kLBlocks, kGBlocks}, {64, 32, 32}, {16, 8, 8}};
+    float et[3];
+    BatchedCfg k2 = best;
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) k2.esc_grid[j] = esc[i][j];
+      if ((e = time_stage(c, k2, 2, s, 3, &et[i])) != hipSuccess) return e;
+    }
+    float tbest = et[0];
+    for (int i = 1; i < 3; ++i) tbest = et[i] < tbest ? et[i] : tbest;
+    int pe = 0;
+    for (int i = 0; i < 3; ++i)
+      if (et[i] <= 1.02f * tbest) pe = i;
+    for (int j = 0; j < 3; ++j) best.esc_grid[j] = esc[pe][j];
     if ((e = enqueue_batched(c, best, s, 2)) != hipSuccess) return e;
   }
   // fit: lanes per event

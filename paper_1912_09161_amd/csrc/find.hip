@@ -1132,7 +1132,15 @@ struct FindCfg {
   uint32_t small_grid;        // 0: one workgroup per event; else persistent work stealing
   const uint32_t* ev_order;   // descending-size order of the events (work stealing)
   uint32_t* counters;         // [3] zeroed work-stealing counters (work stealing)
+  // persistent workgroups of the middle, large and workspace tiers over the
+  // events handed on to them (0: kMBlocks, kLBlocks, kGBlocks; larger values
+  // are clamped to those).  A tier's launch holds its workgroups' LDS until
+  // every one of them has been placed and found the list empty, so a small
+  // grid frees the GPU sooner when few events escalate.
+  uint32_t esc_grid[3];
 };
+
+static uint32_t tier_grid(uint32_t want, uint32_t full) { return want == 0 || want > full ? full : want; }
 
 // ev (may be null): events recorded just before and after the per-event kernel
 hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
@@ -1161,16 +1169,16 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   FindArgs a2 = a;
   a2.esc_count = f.esc2_count;
   a2.esc_list = f.esc2_list;
-  hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), dim3(kMBlocks),
+  hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), dim3(tier_grid(cfg.esc_grid[0], kMBlocks)),
                      dim3(kMThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count,
                      ws_mode ? cfg.counters + 1 : (uint32_t*)nullptr);
   FindArgs a3 = a;
   a3.esc_count = f.esc3_count;
   a3.esc_list = f.esc3_list;
-  hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(kLBlocks),
+  hipLaunchKernelGGL((k_find_lds<kLThreads, kLCapL, kLCapT, kLCapC, kLCapD>), dim3(tier_grid(cfg.esc_grid[1], kLBlocks)),
                      dim3(kLThreads), 0, s, a3, c, n_events, f.esc2_list, f.esc2_count,
                      ws_mode ? cfg.counters + 2 : (uint32_t*)nullptr);
-  hipLaunchKernelGGL(k_find_global, dim3(kGBlocks), dim3(kGThreads), 0, s, a3, c, f.g, f.esc3_list,
+  hipLaunchKernelGGL(k_find_global, dim3(tier_grid(cfg.esc_grid[2], kGBlocks)), dim3(kGThreads), 0, s, a3, c, f.g, f.esc3_list,
                      f.esc3_count);
   return hipGetLastError();
 }
@@ -1179,7 +1187,7 @@ hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_e
                        uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
                        hipStream_t s) {
   return launch_find_cfg(h, offsets, n_events, n_pixels, p, t, ws, s,
-                         FindCfg{kSThreads, 0, nullptr, nullptr});
+                         FindCfg{kSThreads, 0, nullptr, nullptr, {0, 0, 0}});
 }
 
 }  // namespace velo

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_fit_momentum(const float* __restrict__ X
 // pass; every wave handles 64 consecutive tracks (all lanes take part in the
 // matrix instructions), accepted = logit >= threshold.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fit_mlp(const float* __restrict__ X,
                                                          const float* __restrict__ Y,
                                                          const uint32_t* __restrict__ key,
                                                          const uint64_t* __restrict__ offsets,
@@ -258,7 +258,6 @@ __global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
                                                          const float* __restrict__ mstd,
                                                          float threshold, velo_states o) {
   __shared__ MlpLds L;
-  __shared__ MlpWave W[NT / 64];
   mlp_load(L, mp, mmean, mstd, NT);
   __syncthreads();
   const uint32_t e = blockIdx.x;
@@ -267,7 +266,6 @@ __global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
   const uint32_t ne = (uint32_t)(end - b);
   const uint64_t base = b / 3;
   const uint32_t nt = event_tracks(n_tracks[e], ne);
-  MlpWave& Wv = W[threadIdx.x >> 6];
   for (uint32_t t0 = 0; t0 < nt; t0 += NT) {
     const uint32_t t = t0 + threadIdx.x;
     const uint64_t slot = base + t;
@@ -280,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_fit_mlp(const float* __restrict__ X,
     // the whole wave runs the classifier (uniform per wave: t0 is uniform)
     const bool wave_live = __any(ok);
     float z = 0.0f;
-    if (wave_live) z = mlp_wave_logit(L, Wv, feat);
+    if (wave_live) z = mlp_wave_logit(L, feat);
     if (ok) {
       store_state(o, slot, f);
       o.accepted[slot] = (uint8_t)(z >= threshold);

@@ -243,13 +243,6 @@ struct MlpLds {       // per workgroup
   float b1[kNH], b2[kNH], b3, mean[kNF], sd[kNF];
 };
 
-struct MlpWave {      // per wave
-  __bf16 x[64][kNF];
-  __bf16 h1[64][kNH];
-  __bf16 h2[64][kNH];
-  float z[64];
-};
-
 __device__ __forceinline__ void mlp_load(MlpLds& L, const float* __restrict__ P,
                                          const float* __restrict__ mean,
                                          const float* __restrict__ stdv, int nthreads) {
@@ -265,75 +258,90 @@ __device__ __forceinline__ void mlp_load(MlpLds& L, const float* __restrict__ P,
 }
 
 // Logit of the calling lane's sample (raw features f); every lane of the wave
-// must call it (invalid lanes pass any finite values).  Operand layout of
-// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)+i] and
-// B[8(l/16)+i][l%16], and receives D[4(l/16)+i][l%16].
-__device__ __forceinline__ float mlp_wave_logit(const MlpLds& L, MlpWave& W, const float* f) {
+// must call it (invalid lanes pass any finite values).  The wave's 64
+// samples are the columns of the activation matrices and stay in registers.
+// v_mfma_f32_16x16x32_bf16 computes D = A B where lane l = 16 g + r supplies
+// A[r][8g+i] and B[8g+i][r] (i < 8) and receives D[4g+i][r] (i < 4); rows of
+// A and D are units, columns of B and D samples.
+//   Layer 1, sample block m (samples 16m..16m+15), unit block n: B[8g+i][r]
+//   = feature i of the lane's own sample 16g+r, A[r][8g+i] = W1[16n+r][i] for
+//   g == m and 0 otherwise, so only block m's K-slots contribute:
+//   D[4g+i][r] = unit 16n+4g+i of sample 16m+r.
+//   After both unit blocks, lane (g, r) holds for every block m the units
+//   4g..4g+3 and 16+4g..16+4g+3 of sample 16m+r: the 8 K-slots it supplies
+//   to layer 2 when the columns of W2 are taken in that same order.
+//   Layer 3: w3 times the lane's 8 units, summed over the four lanes of the
+//   sample's column (r, 16+r, 32+r, 48+r) by two exchanges, after which
+//   lane 16g+r holds the logit of its own sample (block m = g).
+__device__ __forceinline__ float mlp_wave_logit(const MlpLds& L, const float* f) {
+  // compiler barrier: the weight loads below stay here instead of being
+  // hoisted out of the caller's loop, where they would hold registers
+  // through the whole fit
+  __asm__ volatile("" ::: "memory");
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   bf16x8 xv;
 #pragma unroll
   for (int k = 0; k < kNF; ++k) xv[k] = (__bf16)((f[k] - L.mean[k]) / L.sd[k]);
-  *reinterpret_cast<bf16x8*>(&W.x[lane][0]) = xv;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
   const bf16x8 zero8 = {};
-  // layer 1: K = 8 features padded to 32 (k groups 1..3 are zero)
+  const bf16x8 w1a = *reinterpret_cast<const bf16x8*>(&L.w1[r][0]);
+  const bf16x8 w1b = *reinterpret_cast<const bf16x8*>(&L.w1[16 + r][0]);
+  bf16x8 w2a, w2b;  // rows r and 16 + r of W2, columns 4g..4g+3 and 16+4g..16+4g+3
+  float b1v[8], b2v[8], w3v[8];
 #pragma unroll
-  for (int n = 0; n < 2; ++n) {
-    const bf16x8 b = g == 0 ? *reinterpret_cast<const bf16x8*>(&L.w1[16 * n + r][0]) : zero8;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const bf16x8 a = g == 0 ? *reinterpret_cast<const bf16x8*>(&W.x[16 * m + r][0]) : zero8;
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-      const int u = 16 * n + r;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float h = acc[i] + L.b1[u];
-        W.h1[16 * m + 4 * g + i][u] = (__bf16)(h > 0.0f ? h : 0.0f);
-      }
-    }
+  for (int i = 0; i < 4; ++i) {
+    w2a[i] = L.w2[r][4 * g + i];
+    w2a[4 + i] = L.w2[r][16 + 4 * g + i];
+    w2b[i] = L.w2[16 + r][4 * g + i];
+    w2b[4 + i] = L.w2[16 + r][16 + 4 * g + i];
+    b1v[i] = L.b1[4 * g + i];
+    b1v[4 + i] = L.b1[16 + 4 * g + i];
+    b2v[i] = L.b2[4 * g + i];
+    b2v[4 + i] = L.b2[16 + 4 * g + i];
+    w3v[i] = (float)L.w3[4 * g + i];
+    w3v[4 + i] = (float)L.w3[16 + 4 * g + i];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  // layer 2: K = 32
-#pragma unroll
-  for (int n = 0; n < 2; ++n) {
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(&L.w2[16 * n + r][8 * g]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&W.h1[16 * m + r][8 * g]);
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-      const int u = 16 * n + r;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float h = acc[i] + L.b2[u];
-        W.h2[16 * m + 4 * g + i][u] = (__bf16)(h > 0.0f ? h : 0.0f);
-      }
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  // layer 3: w3 in column 0 of B, the other columns zero
-  const bf16x8 b3 = r == 0 ? *reinterpret_cast<const bf16x8*>(&L.w3[8 * g]) : zero8;
+  const floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f};
+  bf16x8 h1[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(&W.h2[16 * m + r][8 * g]);
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b3, acc, 0, 0, 0);
-    if (r == 0) {
+    const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g == m ? w1a : zero8, xv, acc0, 0, 0, 0);
+    const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g == m ? w1b : zero8, xv, acc0, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) W.z[16 * m + 4 * g + i] = acc[i] + L.b3;
+    for (int i = 0; i < 4; ++i) {
+      const float u0 = d0[i] + b1v[i], u1 = d1[i] + b1v[4 + i];
+      h1[m][i] = (__bf16)(u0 > 0.0f ? u0 : 0.0f);
+      h1[m][4 + i] = (__bf16)(u1 > 0.0f ? u1 : 0.0f);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  return W.z[lane];
+  float p[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2a, h1[m], acc0, 0, 0, 0);
+    const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2b, h1[m], acc0, 0, 0, 0);
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float u0 = d0[i] + b2v[i];
+      s = s + w3v[i] * (float)(__bf16)(u0 > 0.0f ? u0 : 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float u1 = d1[i] + b2v[4 + i];
+      s = s + w3v[4 + i] * (float)(__bf16)(u1 > 0.0f ? u1 : 0.0f);
+    }
+    p[m] = s;
+  }
+  // lanes 32 apart: keep the two blocks whose bit 1 is g's, add the partner's
+  const bool hi = (g >> 1) != 0;
+  float k0 = hi ? p[2] : p[0], k1 = hi ? p[3] : p[1];
+  const float s0 = hi ? p[0] : p[2], s1 = hi ? p[1] : p[3];
+  k0 = k0 + __shfl_xor(s0, 32, 64);
+  k1 = k1 + __shfl_xor(s1, 32, 64);
+  // lanes 16 apart: keep the block whose bit 0 is g's
+  const bool lo = (g & 1) != 0;
+  float z = lo ? k1 : k0;
+  z = z + __shfl_xor(lo ? k0 : k1, 16, 64);
+  return z + L.b3;
 }
 
 constexpr int kInferThreads = 256;
@@ -344,16 +352,14 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_infer(const float* __rest
                                                              const float* __restrict__ feat,
                                                              uint32_t n, float* __restrict__ logit) {
   __shared__ MlpLds L;
-  __shared__ MlpWave W[kInferThreads / 64];
   mlp_load(L, P, mean, stdv, kInferThreads);
   __syncthreads();
-  MlpWave& Wv = W[threadIdx.x >> 6];
   for (uint64_t b0 = (uint64_t)blockIdx.x * kInferThreads; b0 < n; b0 += (uint64_t)gridDim.x * kInferThreads) {
     const uint64_t i = b0 + threadIdx.x;
     float f[kNF];
 #pragma unroll
     for (int k = 0; k < kNF; ++k) f[k] = i < n ? feat[8 * i + k] : L.mean[k];
-    const float z = mlp_wave_logit(L, Wv, f);
+    const float z = mlp_wave_logit(L, f);
     if (i < n) logit[i] = z;
   }
 }

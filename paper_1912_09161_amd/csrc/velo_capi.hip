@@ -266,7 +266,7 @@ velo_status velo_reconstruct_timed(const uint32_t* d_pixels, const uint64_t* d_o
                                           velo::ClusterCfg{0, 512, nullptr, nullptr}, false, ev6);
   if (e == hipSuccess)
     e = velo::launch_find_cfg(hits, d_offsets, n_events, n_pixels, params, tracks, d_ws, stream,
-                              velo::FindCfg{velo::kSThreads, 0, nullptr, nullptr}, ev6 + 2);
+                              velo::FindCfg{velo::kSThreads, 0, nullptr, nullptr, {0, 0, 0}}, ev6 + 2);
   if (e == hipSuccess)
     e = velo::launch_fit_cfg(hits, tracks, d_offsets, n_events, n_pixels, params, nullptr, states,
                              stream, velo::kFitThreads, ev6 + 4);
@@ -378,13 +378,17 @@ void velo_context_destroy(velo_context* ctx) {
   delete ctx;
 }
 
-velo_status velo_context_set_config(velo_context* ctx, const int32_t* in5) {
-  if (!ctx || !in5) return VELO_ERR_ARG;
-  const int32_t cg = in5[0], mg = in5[1], ft = in5[2], fg = in5[3], fit = in5[4];
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in8) {
+  if (!ctx || !in8) return VELO_ERR_ARG;
+  const int32_t cg = in8[0], mg = in8[1], ft = in8[2], fg = in8[3], fit = in8[4];
   if (cg < 0 || cg > 65536 || mg < 1 || mg > 65536 || (ft != 128 && ft != 256) || fg < 0 ||
       fg > 65536 || (fit != 64 && fit != 128 && fit != 256))
     return VELO_ERR_ARG;
-  ctx->cfg = velo::BatchedCfg{(uint32_t)cg, (uint32_t)mg, ft, (uint32_t)fg, fit};
+  const uint32_t full[3] = {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks};
+  for (int i = 0; i < 3; ++i)
+    if (in8[5 + i] < 1 || (uint32_t)in8[5 + i] > full[i]) return VELO_ERR_ARG;
+  ctx->cfg = velo::BatchedCfg{(uint32_t)cg, (uint32_t)mg, ft, (uint32_t)fg, fit,
+                              {(uint32_t)in8[5], (uint32_t)in8[6], (uint32_t)in8[7]}};
   ctx->tuned = true;
   ctx->source = 3;
   for (int i = 0; i < 5; ++i) ctx->tuned_ms[i] = 0.0f;
@@ -392,14 +396,15 @@ velo_status velo_context_set_config(velo_context* ctx, const int32_t* in5) {
   return VELO_OK;
 }
 
-velo_status velo_context_config(const velo_context* ctx, int32_t* out6, float* tuned_ms5) {
-  if (!ctx || !out6) return VELO_ERR_ARG;
-  out6[0] = ctx->tuned ? ctx->source : 0;
-  out6[1] = (int32_t)ctx->cfg.small_grid;
-  out6[2] = (int32_t)ctx->cfg.mid_grid;
-  out6[3] = ctx->cfg.find_threads;
-  out6[4] = (int32_t)ctx->cfg.find_grid;
-  out6[5] = ctx->cfg.fit_threads;
+velo_status velo_context_config(const velo_context* ctx, int32_t* out9, float* tuned_ms5) {
+  if (!ctx || !out9) return VELO_ERR_ARG;
+  out9[0] = ctx->tuned ? ctx->source : 0;
+  out9[1] = (int32_t)ctx->cfg.small_grid;
+  out9[2] = (int32_t)ctx->cfg.mid_grid;
+  out9[3] = ctx->cfg.find_threads;
+  out9[4] = (int32_t)ctx->cfg.find_grid;
+  out9[5] = ctx->cfg.fit_threads;
+  for (int i = 0; i < 3; ++i) out9[6 + i] = (int32_t)ctx->cfg.esc_grid[i];
   if (tuned_ms5)
     for (int i = 0; i < 5; ++i) tuned_ms5[i] = ctx->tuned_ms[i];
   return VELO_OK;

@@ -65,21 +65,32 @@ __device__ __forceinline__ void wg_barrier() {
   }
 }
 
+// Inclusive scan of v over the 64 lanes of the calling wave without LDS
+// round trips: Hillis-Steele steps inside each 16-lane row by DPP row shifts
+// (1, 2, 4, 8; lanes shifted in from outside the row read 0), then the row
+// totals carried across rows by the row_bcast:15 (rows 1, 3) and
+// row_bcast:31 (rows 2, 3) broadcasts.  Every lane of the wave must be
+// active (all callers are in wave-uniform control flow).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  uint32_t x = v;
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);   // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);   // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
 // Workgroup exclusive scan of one value per thread; NT threads, `tmp` holds
 // NT/64 + 1 uint32 of LDS.  Returns the exclusive prefix; *total = sum.
 template <int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   constexpr int NW = NT / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  // inclusive wave scan
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_incl_scan(v);
   if constexpr (NW == 1) {
-    *total = __shfl(x, kWave - 1, kWave);
+    *total = __builtin_amdgcn_readlane(x, kWave - 1);
     return x - v;
   } else {
     if (lane == kWave - 1) tmp[wid] = x;
@@ -104,14 +115,9 @@ template <int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ uint32_t block_scan1(uint32_t v, uint32_t* tmp, uint32_t* total) {
   constexpr int NW = NT / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_incl_scan(v);
   if constexpr (NW == 1) {
-    *total = __shfl(x, kWave - 1, kWave);
+    *total = __builtin_amdgcn_readlane(x, kWave - 1);
     return x - v;
   } else {
     if (lane == kWave - 1) tmp[wid] = x;

@@ -7,8 +7,10 @@ a time, and the outputs of each are compared with the oracle element by
 element: clustering one workgroup per segment or persistent grids of 1024 to
 8192 workgroups (with 256 to 1024 large-segment workgroups), track finding
 with 128 or 256 lanes per event, one workgroup per event or persistent grids
-of 512 to 1536, the fit with 64 to 256 lanes.  Events of uneven occupancy and
-high-occupancy events (where the larger track-finding tiers run).
+of 512 to 1536, the fit with 64 to 256 lanes, the tiers that take the
+escalated events with grids from their full size down to one workgroup.
+Events of uneven occupancy and high-occupancy events (where the larger
+track-finding tiers run).
 """
 import numpy as np
 import pytest
@@ -21,15 +23,19 @@ pytestmark = pytest.mark.gpu
 CLUSTER = [(cg, mg) for cg in (0, 1024, 2048, 4096, 8192) for mg in (256, 512, 1024)]
 FIND = [(nt, g) for nt in (128, 256) for g in (0, 512, 768, 1024, 1536)]
 FIT = [64, 128, 256]
-BASE = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128)
+TIERS = [(64, 32, 32), (16, 8, 8), (1, 1, 1)]
+BASE = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
+            tier_grids=(512, 256, 128))
 
 
 def shapes():
     out = [dict(BASE, cluster_grid=cg, mid_grid=mg) for cg, mg in CLUSTER]
     out += [dict(BASE, find_threads=nt, find_grid=g) for nt, g in FIND]
     out += [dict(BASE, fit_threads=f) for f in FIT]
+    out += [dict(BASE, tier_grids=t) for t in TIERS]
     # all persistent at once
-    out.append(dict(cluster_grid=2048, mid_grid=512, find_threads=256, find_grid=1024, fit_threads=128))
+    out.append(dict(cluster_grid=2048, mid_grid=512, find_threads=256, find_grid=1024, fit_threads=128,
+                    tier_grids=(16, 8, 8)))
     return out
 
 
@@ -57,6 +63,7 @@ def test_every_launch_shape_equals_oracle(orc, name, n, xl):
         ctx.set_config(**sh)
         cfg = ctx.config()
         assert cfg["source"] == "set" and cfg["find_grid"] == sh["find_grid"]
+        assert cfg["tier_grids"] == list(sh["tier_grids"])
         if bufs is not None:  # stale outputs of the previous shape must be overwritten
             for k in ("n_tracks", "nhits"):
                 bufs["tracks"][k].fill_(7)
@@ -74,7 +81,8 @@ def test_set_config_rejects_bad_shapes():
     import paper_1912_09161_amd as velo
     ctx = velo.Context()
     for bad in (dict(find_threads=192), dict(fit_threads=32), dict(mid_grid=0), dict(cluster_grid=-1),
-                dict(find_grid=70000)):
+                dict(find_grid=70000), dict(tier_grids=(0, 8, 8)), dict(tier_grids=(513, 8, 8)),
+                dict(tier_grids=(16, 257, 8)), dict(tier_grids=(16, 8, 129))):
         with pytest.raises(velo.VeloError):
             ctx.set_config(**dict(BASE, **bad))
     assert ctx.config()["source"] == "untuned"
@@ -97,7 +105,7 @@ def test_tune_cache_serves_a_new_context():
     torch.cuda.synchronize()
     k1, k2 = c1.config(), c2.config()
     assert k1["source"] == "tuned" and k2["source"] == "tune cache"
-    for k in ("cluster_grid", "mid_grid", "find_threads", "find_grid", "fit_threads"):
+    for k in ("cluster_grid", "mid_grid", "find_threads", "find_grid", "fit_threads", "tier_grids"):
         assert k1[k] == k2[k]
     for part in ("hits", "tracks"):
         for k, v in r1[part].items():
