@@ -322,23 +322,33 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
   BatchedCfg best = ctx->cfg;
   float t;
   hipError_t e;
-  // clustering: one workgroup per segment, or persistent grids of several sizes
+  // clustering: one workgroup per segment, or persistent grids of several
+  // sizes; then the smallest large-segment grid within 2 % of the chosen
+  // time (like the track-finding tiers below, a persistent launch with LDS-
+  // heavy workgroups holds its reservations until every workgroup is placed)
   {
     const uint32_t smalls[] = {0, 1024, 2048, 4096, 8192};
-    const uint32_t mids[] = {256, 512, 1024};
+    constexpr int kNM = 4;
+    const uint32_t mids[kNM] = {1024, 512, 256, 64};
     float bt[2] = {1e30f, 1e30f};  // one workgroup per segment, persistent
+    float tm[5][kNM];
     BatchedCfg k = best, pick[2] = {best, best};
-    for (uint32_t sg : smalls)
-      for (uint32_t mg : mids) {
-        k.small_grid = sg;
-        k.mid_grid = mg;
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < kNM; ++j) {
+        k.small_grid = smalls[i];
+        k.mid_grid = mids[j];
         if ((e = time_stage(c, k, 1, s, 3, &t)) != hipSuccess) return e;
-        const int p = sg != 0;
+        tm[i][j] = t;
+        const int p = smalls[i] != 0;
         if (t < bt[p]) { bt[p] = t; pick[p] = k; }
       }
     const int p = bt[1] < kPersistentGain * bt[0];
     best.small_grid = pick[p].small_grid;
     best.mid_grid = pick[p].mid_grid;
+    for (int i = 0; i < 5; ++i)
+      if (smalls[i] == best.small_grid)
+        for (int j = 0; j < kNM; ++j)
+          if (tm[i][j] <= 1.02f * bt[p]) best.mid_grid = mids[j];
     ctx->tuned_ms[0] = bt[p];
     ctx->tuned_ms[3] = bt[0];
     if ((e = enqueue_batched(c, best, s, 1)) != hipSuccess) return e;

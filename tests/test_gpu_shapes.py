@@ -5,7 +5,7 @@ tuning stream, so which kernels run depends on the workload.  Here every
 candidate shape is fixed through velo_context_set_config, one stage varied at
 a time, and the outputs of each are compared with the oracle element by
 element: clustering one workgroup per segment or persistent grids of 1024 to
-8192 workgroups (with 256 to 1024 large-segment workgroups), track finding
+8192 workgroups (with 64 to 1024 large-segment workgroups), track finding
 with 128 or 256 lanes per event, one workgroup per event or persistent grids
 of 512 to 1536, the fit with 64 to 256 lanes, the tiers that take the
 escalated events with grids from their full size down to one workgroup.
@@ -20,7 +20,7 @@ from synth import generate
 
 pytestmark = pytest.mark.gpu
 
-CLUSTER = [(cg, mg) for cg in (0, 1024, 2048, 4096, 8192) for mg in (256, 512, 1024)]
+CLUSTER = [(cg, mg) for cg in (0, 1024, 2048, 4096, 8192) for mg in (64, 256, 512, 1024)]
 FIND = [(nt, g) for nt in (128, 256) for g in (0, 512, 768, 1024, 1536)]
 FIT = [64, 128, 256]
 TIERS = [(64, 32, 32), (16, 8, 8), (1, 1, 1)]
