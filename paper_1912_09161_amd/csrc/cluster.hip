@@ -122,6 +122,7 @@ struct SegScratch {
 template <int NT, bool PACKED, uint32_t MAXW>
 __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, uint32_t layer,
                                     const SegScratch<PACKED>& S, HitsOut o, uint64_t out_base) {
+  constexpr uint32_t WPL = (RowTab<PACKED>::kWords + NT - 1) / NT;  // row words per lane
   const uint32_t tid = threadIdx.x;
   const RowTab<PACKED> rt{S.rows};
   constexpr uint32_t RW = MAXW > 0 ? MAXW : 1;
@@ -144,20 +145,27 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
     for (uint32_t i = tid; i < n; i += NT) rt.add(w_row(w[i]));
   }
   __syncthreads();
-  {  // row starts: exclusive prefix over the row words, NT consecutive words
-     // per pass (consecutive lanes touch consecutive words: no bank conflicts)
-    uint32_t carry = 0;
+  {  // row starts: exclusive prefix over rows, WPL consecutive words per lane
+    const uint32_t w0 = tid * WPL;
+    uint32_t c[WPL], sum = 0;
 #pragma unroll
-    for (uint32_t w0 = 0; w0 < RowTab<PACKED>::kWords; w0 += NT) {
-      const uint32_t wi = w0 + tid;
-      const uint32_t c = wi < RowTab<PACKED>::kWords ? ld(S.rows + wi) : 0u;
-      uint32_t tot;
-      const uint32_t run = carry + block_scan<NT>(PACKED ? (c & 0xFFFFu) + (c >> 16) : c, S.tmp, &tot);
-      if (wi < RowTab<PACKED>::kWords) {
-        if constexpr (PACKED) S.rows[wi] = run | ((run + (c & 0xFFFFu)) << 16);
-        else S.rows[wi] = run;
+    for (uint32_t k = 0; k < WPL; ++k) {
+      c[k] = w0 + k < RowTab<PACKED>::kWords ? ld(S.rows + w0 + k) : 0u;
+      sum += PACKED ? (c[k] & 0xFFFFu) + (c[k] >> 16) : c[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_scan<NT>(sum, S.tmp, &tot);
+#pragma unroll
+    for (uint32_t k = 0; k < WPL; ++k) {
+      if (w0 + k >= RowTab<PACKED>::kWords) continue;
+      if constexpr (PACKED) {
+        const uint32_t lo = run, hi = run + (c[k] & 0xFFFFu);
+        S.rows[w0 + k] = lo | (hi << 16);
+        run = hi + (c[k] >> 16);
+      } else {
+        S.rows[w0 + k] = run;
+        run += c[k];
       }
-      carry += tot;
     }
   }
   __syncthreads();
