@@ -68,10 +68,14 @@ def parse():
                     help="rounds over all batches of the one-stream kernel-timing pass")
     ap.add_argument("--train-events", type=int, default=5500)
     ap.add_argument("--val-events", type=int, default=2000)
-    ap.add_argument("--physics-events", type=int, default=2000, help="held-out test events for efficiency")
-    ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--ghost-weight", type=float, default=1.0,
-                    help="ghost tracks drawn this many times as often in training")
+    ap.add_argument("--physics-events", type=int, default=10000, help="held-out test events for efficiency")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--ghost-weight", type=float, default=64.0,
+                    help="ghost tracks drawn this many times as often in training (nominal occupancy: "
+                         "ghosts are 0.085 %% of the tracks)")
+    ap.add_argument("--stress-epochs", type=int, default=8)
+    ap.add_argument("--stress-ghost-weight", type=float, default=1.0,
+                    help="the same at high occupancy (ghosts are about 4 %% of the tracks)")
     ap.add_argument("--stress-events", type=int, default=2000, help="0: skip the high-occupancy leg")
     ap.add_argument("--stress-train", type=int, default=1500)
     ap.add_argument("--stress-val", type=int, default=1000)
@@ -454,7 +458,7 @@ def main():
         if not args.no_learned:
             mlp_s, info_s = train(velo, torch, generate("stress", args.stress_train, workers=THREADS),
                                   generate("stress", args.stress_val, first_event=4096, workers=THREADS), sp,
-                                  args.epochs, args.ghost_weight, dev)
+                                  args.stress_epochs, args.stress_ghost_weight, dev)
             sbt = Batched(velo, SB, ss, sp, mlp_s)
             w, _ = measure(torch, lambda b: sbt(b % len(SB)), len(ss), E, n_st, args.warmup, 0)
             stress["batched_mlp"] = dict(value=round(n_st * len(ss) * E / w, 1), training=info_s,

@@ -18,7 +18,7 @@ import json
 import sys
 from collections import defaultdict
 
-STAGE_OF = [("k_validate", "cluster"), ("k_small", "cluster"), ("k_mid", "cluster"),
+STAGE_OF = [("k_offsets", "cluster"), ("k_validate", "cluster"), ("k_small", "cluster"), ("k_mid", "cluster"),
             ("k_finalize", "cluster"), ("k_phi_tables", "find_tracks"), ("k_find", "find_tracks"),
             ("k_fit", "fit")]
 
