@@ -26,8 +26,9 @@ std); the HBM roofline of the dominant kernel, timed by itself with HIP
 events on its stream in a one-stream pass over all batches; efficiency,
 ghost and clone rates of both forms on held-out events; the streaming form
 (host memory in, compact tracks and vertices out, thread-stream pairs, with
-and without the global event cut); the high-occupancy sample; the CPU oracle
-on a bounded sample.
+and without the global event cut); 100k events of uneven occupancy in one
+launch (plain and batched + classifier); the high-occupancy sample; the CPU
+oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -46,11 +47,13 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("nominal occupancy: 1000 events per batch, 26 planes, PVs/event Poisson(7.6), "
             "tracks/PV Poisson(25), 98% hit efficiency, 1-3 px clusters, noise 1e-5/px, "
             "50 urad scattering; uint32 raw words, binary32 hits and fits")
+UNEVEN = ("uneven occupancy in one launch: PVs/event uniform 1..15 (about 25-375 tracks per event), "
+          "otherwise nominal")
 STRESS = ("high occupancy: PVs/event Poisson(20), noise 1e-4/px, 95% hit efficiency, 100 urad "
           "scattering, X/X0 2.38e-3 per plane")
 THREADS = os.cpu_count() or 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "velo_hbm_traffic_nominal.json")
-DOMINANT_KERNEL = {"cluster": "k_small", "find_tracks": "k_find_lds<256, 352u, 320u, 384u, 960u>",
+DOMINANT_KERNEL = {"cluster": "k_small", "find_tracks": "k_find_lds<256, 288u, 256u, 384u, 768u>",
                    "fit": "k_fit<256>"}
 
 
@@ -77,6 +80,9 @@ def parse():
     ap.add_argument("--stress-ghost-weight", type=float, default=1.0,
                     help="the same at high occupancy (ghosts are about 4 %% of the tracks)")
     ap.add_argument("--stress-events", type=int, default=2000, help="0: skip the high-occupancy leg")
+    ap.add_argument("--uneven-events", type=int, default=100000,
+                    help="events of uneven occupancy reconstructed in one launch (0: skip that leg)")
+    ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--stress-train", type=int, default=1500)
     ap.add_argument("--stress-val", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -441,6 +447,27 @@ def main():
     del plain, B
     torch.cuda.empty_cache()
 
+    # ---- uneven occupancy, every event in one launch (the batched form's own workload)
+    uneven = None
+    if args.uneven_events > 0:
+        t1 = time.time()
+        ub = generate("uneven", args.uneven_events, workers=THREADS)
+        ugen = time.time() - t1
+        UB = batches_to_device(velo, torch, [ub], dev)
+        s0 = streams[0]
+        up = Plain(velo, UB, [s0], params)
+        uneven = dict(workload=UNEVEN, events=ub.n_events, pixels_per_event=round(ub.n_pixels / ub.n_events, 1),
+                      steps=args.uneven_steps, gen_seconds=round(ugen, 1))
+        w, _ = measure(torch, lambda b: up(0), 1, ub.n_events, args.uneven_steps, 1, 0)
+        uneven["plain"] = dict(value=round(args.uneven_steps * ub.n_events / w, 1))
+        if mlp_nominal is not None:
+            ubt = Batched(velo, UB, [s0], params, mlp_nominal)
+            w, _ = measure(torch, lambda b: ubt(0), 1, ub.n_events, args.uneven_steps, 1, 0)
+            uneven["batched_mlp"] = dict(value=round(args.uneven_steps * ub.n_events / w, 1), autotuned=ubt.close())
+        del up, UB
+        torch.cuda.empty_cache()
+        log(f"uneven: plain {uneven['plain']['value']:.0f} events/s")
+
     # ---- high occupancy
     stress = None
     if args.stress_events > 0:
@@ -504,6 +531,8 @@ def main():
 
     gates = dict(
         batched_mlp_ge_plain=None if args.no_learned else bool(headline >= plain_value),
+        batched_mlp_ge_plain_uneven=None if not uneven or "batched_mlp" not in uneven
+        else bool(uneven["batched_mlp"]["value"] >= uneven["plain"]["value"]),
         ghost_reduction_ge_20pct=None if not phys or "ghost_rate_reduction" not in phys
         else bool((phys["ghost_rate_reduction"] or 0) >= 0.2 and phys["efficiency_not_lower"]),
         cluster_hbm_frac=next(k["frac"] for k in kernels if k["stage"] == "cluster"),
@@ -518,7 +547,8 @@ def main():
                     form="plain" if args.no_learned else "batched_mlp",
                     pixels_per_event=round(allb.n_pixels / allb.n_events, 1),
                     per_batch=dict(hits=counts["hits"], tracks=counts["tracks"], track_hits=counts["track_hits"])),
-        roofline=roofline, kernels=kernels, forms=forms, gates=gates, physics=phys, e2e=e2e, stress=stress,
+        roofline=roofline, kernels=kernels, forms=forms, gates=gates, physics=phys, e2e=e2e, uneven=uneven,
+        stress=stress,
         cpu_baseline=cpu, cpu_baseline_1thread=cpu1, gen_seconds=round(gen_s, 1))
     print(json.dumps(out))
 

@@ -53,13 +53,13 @@ struct LayerTab {
   const IDX* kr;          // local index of the hit at each position
   uint8_t* used;
   SLOT* best;             // round winner at the hit (see Cands)
-  const uint32_t* bstart; // [kNB + 1] first position of every bucket
+  const IDX* bstart;      // [kNB + 1] first position of every bucket
 };
 
-template <typename SLOT>
+template <typename SLOT, typename K>
 struct TrackTab {
-  uint32_t* slot;   // output slot
-  uint32_t* key0;   // first hit: plane << KSH | local index (orders like its key)
+  K* slot;          // output slot, counted from the event's first track slot
+  K* key0;          // first hit: plane << KSH | local index (orders like its key)
   float* xa;        // last hit
   float* ya;
   float* tx;        // slope through the last two hits
@@ -119,8 +119,8 @@ struct FindMem {
   IDX* kr;
   uint8_t* used;
   SLOT* best;
-  uint32_t* bstart;  // [3 * (kNB + 1)]
-  TrackTab<SLOT> T;
+  IDX* bstart;       // [3 * (kNB + 1)]
+  TrackTab<SLOT, IDX> T;
   Cand* cand;        // workspace tier
   uint64_t* cprio;   // LDS tiers
   uint32_t* cpos;
@@ -246,7 +246,7 @@ struct PlanePrefetch {
       float* hx = const_cast<float*>(t.hx);
       float* hy = const_cast<float*>(t.hy);
       IDX* kr = const_cast<IDX*>(t.kr);
-      uint32_t* bsd = const_cast<uint32_t*>(t.bstart);
+      IDX* bsd = const_cast<IDX*>(t.bstart);
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
@@ -255,7 +255,7 @@ struct PlanePrefetch {
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
         const uint32_t b = threadIdx.x + k * NT;
-        if (b <= kNB) bsd[b] = bs[k];
+        if (b <= kNB) bsd[b] = (IDX)bs[k];
       }
     }
   }
@@ -520,7 +520,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         const uint32_t h = A.tmatch[t];
         if (h != kNone) {
           const uint32_t nn = A.n[t];
-          io.hit_idx[26ull * A.slot[t] + nn] = base0 + (uint32_t)T0.kr[h];
+          io.hit_idx[26ull * (io.slot_base + A.slot[t]) + nn] = base0 + (uint32_t)T0.kr[h];
           const float xh = T0.hx[h], yh = T0.hy[h];
           const float dz = zl - zt[A.la[t]];
           A.tx[t] = (xh - A.xa[t]) / dz;
@@ -533,7 +533,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         } else {
           const int sk = A.skip[t] + 1;
           A.skip[t] = (uint8_t)sk;
-          if (sk > P.max_skip) io.nhits[A.slot[t]] = A.n[t];
+          if (sk > P.max_skip) io.nhits[io.slot_base + A.slot[t]] = A.n[t];
         }
       }
     }
@@ -799,8 +799,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       } else {
         const Cand c = M.cand[k]; cb = c.b; cc = c.c;
       }
-      const uint32_t slot = (uint32_t)io.slot_base + created + rank;
-      uint32_t* hi = io.hit_idx + 26ull * slot;
+      uint32_t* hi = io.hit_idx + 26ull * (io.slot_base + created + rank);
       hi[0] = io.lstart[l + 2] + i0;
       hi[1] = io.lstart[l + 1] + (uint32_t)T1.kr[cb];
       hi[2] = base0 + (uint32_t)T0.kr[cc];
@@ -808,8 +807,8 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       if (pos < M.capT) {
         const float x1 = T1.hx[cb], y1 = T1.hy[cb], x2 = T0.hx[cc], y2 = T0.hy[cc];
         const float dz = zl - zt[l + 1];
-        A.slot[pos] = slot;
-        A.key0[pos] = ((uint32_t)(l + 2) << M.KSH) | i0;
+        A.slot[pos] = (IDX)(created + rank);
+        A.key0[pos] = (IDX)(((uint32_t)(l + 2) << M.KSH) | i0);
         A.xa[pos] = x2;
         A.ya[pos] = y2;
         A.tx[pos] = (x2 - x1) / dz;
@@ -824,7 +823,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       return Keep{A.slot[t], A.key0[t], A.xa[t], A.ya[t], A.tx[t], A.ty[t], A.la[t], A.n[t], A.skip[t]};
     };
     auto write_keep = [&](uint32_t pos, const Keep& f) {
-      A.slot[pos] = f.slot; A.key0[pos] = f.key0; A.xa[pos] = f.xa; A.ya[pos] = f.ya;
+      A.slot[pos] = (IDX)f.slot; A.key0[pos] = (IDX)f.key0; A.xa[pos] = f.xa; A.ya[pos] = f.ya;
       A.tx[pos] = f.tx; A.ty[pos] = f.ty; A.la[pos] = f.la; A.n[pos] = f.n; A.skip[pos] = f.skip;
     };
     uint32_t n_keep;
@@ -873,7 +872,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     wg_barrier<RING>();
   }
   // close the tracks still active after the first plane
-  for (uint32_t t = tid; t < sc.n_act; t += NT) io.nhits[A.slot[t]] = A.n[t];
+  for (uint32_t t = tid; t < sc.n_act; t += NT) io.nhits[io.slot_base + A.slot[t]] = A.n[t];
   wg_barrier<RING>();
   return 0u;
 }
@@ -955,7 +954,7 @@ __device__ __forceinline__ bool run_event(const FindArgs& a, const FindConst& P,
 // LDS tiers: one event per workgroup (list == nullptr) or a persistent loop
 // over a list of events.
 template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t CAPD>
-__global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 5 : 1))) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
                                                  const uint32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ list_count,
                                                  uint32_t* __restrict__ steal) {
@@ -963,8 +962,8 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   __shared__ uint16_t s_kr[3 * CAPL];
   __shared__ uint8_t s_used[3 * CAPL];
   __shared__ uint64_t s_best[3 * CAPL];
-  __shared__ uint32_t s_bstart[3 * (kNB + 1)];
-  __shared__ uint32_t t_slot[CAPT], t_key0[CAPT];
+  __shared__ uint16_t s_bstart[3 * (kNB + 1)];
+  __shared__ uint16_t t_slot[CAPT], t_key0[CAPT];
   __shared__ float t_xa[CAPT], t_ya[CAPT], t_tx[CAPT], t_ty[CAPT];
   __shared__ uint8_t t_la[CAPT], t_n[CAPT], t_skip[CAPT];
   // candidates (priorities, positions) share their space with the seed doublet
@@ -988,7 +987,8 @@ __global__ __launch_bounds__(NT) void k_find_lds(FindArgs a, FindConst P, uint32
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
   M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
   M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
-  M.T = TrackTab<uint64_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest, t_tmatch};
+  M.T = TrackTab<uint64_t, uint16_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest,
+                                     t_tmatch};
   M.cand = nullptr;
   M.cprio = s_cw;
   M.cpos = cw + 2 * CAPC;
@@ -1030,7 +1030,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.used = g.used + b;
     M.best = g.best + b;
     const uint64_t tb = b / 3;
-    M.T = TrackTab<uint32_t>{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
+    M.T = TrackTab<uint32_t, uint32_t>{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
                    g.la + tb, g.n + tb, g.skip + tb, g.tbest + tb, g.tmatch + tb};
     M.cand = g.cand + (size_t)blockIdx.x * VELO_MAX_CANDIDATES;
     M.cprio = nullptr;
@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
-constexpr uint32_t kSCapL = 352, kSCapT = 320, kSCapC = 384, kSCapD = 3 * kSCapT;
+constexpr uint32_t kSCapL = 288, kSCapT = 256, kSCapC = 384, kSCapD = 3 * kSCapT;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;

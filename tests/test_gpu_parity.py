@@ -157,10 +157,11 @@ def test_fit_checks_caller_tracks():
 
 
 def test_small_tier_capacity_edges(orc):
-    """Events at the limits of the small track-finding tier: 352 hits on one
-    plane (the most it holds) and 353 (handed to the middle tier before any
-    work), and 340 long straight lines from the origin, seen on both sides of
-    it, with more active tracks and seed doublets than the small tier holds (handed
+    """Events at the limits of the small track-finding tier: 288 hits on one
+    plane (the most it holds) and 289 (handed to the middle tier before any
+    work); 256 and 257 long straight lines from the origin (the most active
+    tracks it holds, and one more), and 340, seen on both sides of it, with
+    more active tracks and seed doublets than the small tier holds (handed
     over part way through); every event equals the oracle."""
     def grid_plane(l, n):  # n isolated pixels on plane l
         return [word(l, 100 + 2 * (k // 600), 100 + 2 * (k % 600), 3) for k in range(n)]
@@ -169,14 +170,17 @@ def test_small_tier_capacity_edges(orc):
         return sorted(dict.fromkeys(int(w) for w in ws), key=lambda w: (w >> 22) & 31)
 
     good = line_event([(0.02 * 600, 0.015 * 600, 0.02, 0.015)])
-    lines = [(0.0, 0.0, 0.05 * np.cos(2 * np.pi * k / 340 + 0.01), 0.05 * np.sin(2 * np.pi * k / 340 + 0.01))
-             for k in range(340)]
-    events = [by_plane(good + grid_plane(20, 351)), by_plane(good + grid_plane(20, 352)),
-              by_plane(line_event(lines)), good]
+    def lines(m):
+        return [(0.0, 0.0, 0.05 * np.cos(2 * np.pi * k / m + 0.01), 0.05 * np.sin(2 * np.pi * k / m + 0.01))
+                for k in range(m)]
+    events = [by_plane(good + grid_plane(20, 287)), by_plane(good + grid_plane(20, 288)),
+              by_plane(line_event(lines(340))), by_plane(line_event(lines(256))),
+              by_plane(line_event(lines(257))), good]
     px, off = pack(events)
     g, o, _ = run_pair(orc, px, off)
     per_plane = o["hits"]["layer_nhits"].reshape(-1, 26).max(1)
-    assert per_plane[0] == 352 and per_plane[1] == 353 and per_plane[2] == 340
+    assert per_plane[0] == 288 and per_plane[1] == 289 and per_plane[2] == 340
+    assert per_plane[3] == 256 and per_plane[4] == 257
     assert o["tracks"]["n_tracks"][2] > 600
 
 
