@@ -310,10 +310,11 @@ __device__ __forceinline__ void validate_words(const uint32_t* __restrict__ w, u
 // Usable offsets: event e owns words [offsets[e], offsets[e+1]) only if
 // offsets[e] <= offsets[e+1] <= n_pixels and no earlier offset exceeds
 // offsets[e] (offsets[e] is the running maximum of offsets[0..e]); then the
-// word ranges of usable events are disjoint.  One 1024-lane workgroup walks
-// the offsets in tiles of 1024 events, carrying the running maximum from tile
-// to tile, and writes status[e] = 0 or VELO_EV_BAD_OFFSETS.
-constexpr int kOffThreads = 1024;
+// word ranges of usable events are disjoint.  One 256-lane workgroup walks
+// the offsets in tiles of 256 events, carrying the running maximum from tile
+// to tile, and writes status[e] = 0 or VELO_EV_BAD_OFFSETS.  (A small
+// workgroup finds a place on a GPU busy with other streams' work sooner.)
+constexpr int kOffThreads = 256;
 __global__ __launch_bounds__(kOffThreads) void k_offsets(const uint64_t* __restrict__ offsets,
                                                          uint32_t n_events, uint64_t n_pixels,
                                                          uint32_t* __restrict__ status) {
