@@ -19,7 +19,8 @@ import sys
 from collections import defaultdict
 
 STAGE_OF = [("k_offsets", "cluster"), ("k_validate", "cluster"), ("k_small", "cluster"), ("k_mid", "cluster"),
-            ("k_finalize", "cluster"), ("k_phi_tables", "find_tracks"), ("k_find", "find_tracks"),
+            ("k_finalize", "cluster"), ("k_clear_counts", "find_tracks"), ("k_phi_tables", "find_tracks"),
+            ("k_find", "find_tracks"),
             ("k_fit", "fit")]
 
 

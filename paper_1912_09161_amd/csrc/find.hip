@@ -3,13 +3,13 @@
 // planes, extended to the other planes along straight lines; hits of every
 // plane kept in azimuth order for fast look-up).
 //
-// k_phi_tables first sorts the hits of every (event, plane) into kNB azimuth
-// buckets of a monotone pseudo-angle of (x, y) (one wave per plane, counting
-// sort) and writes their coordinates in that order.  Then one workgroup per
-// event walks the planes from z = +750 mm down; the three planes in use
-// (l+2, l+1, l) are staged in a ring of LDS tables indexed by bucket position:
-// coordinates, the hit's index in key order, used flags.  A window scan thus
-// reads the coordinates of consecutive positions directly.  Candidate windows in
+// One workgroup per event walks the planes from z = +750 mm down; the three
+// planes in use (l+2, l+1, l) are staged in a ring of LDS tables indexed by
+// bucket position: the hits of a plane are read in key order and counting-
+// sorted into kNB azimuth buckets of a monotone pseudo-angle of (x, y) while
+// they are staged (coordinates, the hit's index in key order, bucket starts;
+// used flags).  A window scan thus reads the coordinates of consecutive
+// positions directly.  Candidate windows in
 // pseudo-angle are derived conservatively from the exact cuts, so they only
 // accelerate; every decision uses the exact binary32 cut expressions.
 //
@@ -26,9 +26,9 @@
 //
 // Four tiers share one implementation: a 256-lane workgroup per event with
 // small LDS tables, persistent 512- and 1024-lane workgroups with middle and
-// large LDS tables, and 256 lanes reading the bucket tables in place with
-// per-event scratch in the caller's workspace at the event's own hit / track
-// positions.  An event whose tables outgrow its tier is re-run from scratch by
+// large LDS tables, and 256 lanes that first write the event's bucket tables
+// to the workspace and then read them in place, with per-event scratch in the
+// caller's workspace at the event's own hit / track positions.  An event whose tables outgrow its tier is re-run from scratch by
 // the next tier.
 #include "azimuth.hpp"
 
@@ -94,8 +94,10 @@ constexpr uint32_t kPosBits = 10, kPosMask = (1u << kPosBits) - 1u, kAccepted = 
 using Dbl = uint32_t;
 
 struct EventIO {
-  const float* X;          // coordinates of the event's hits in bucket order
+  const float* X;          // coordinates of the event's hits in bucket order (workspace tier)
   const float* Y;          // (absolute base applied)
+  const float* HX;         // coordinates of the event's hits in key order (the LDS tiers
+  const float* HY;         // sort them into the ring themselves)
   const uint32_t* lstart;  // [27]
   const uint32_t* lnh;     // [26]
   const uint32_t* order;   // local index at every bucket position (at the hits' slots)
@@ -135,6 +137,7 @@ struct FindMem {
   uint32_t* tw1;
   uint32_t* twp;  // [capT + 1]
   Dbl* dbl;       // [capD]
+  uint32_t* cnt;  // [kNB / 2] bucket counters of the plane being staged, 16 bits each (LDS tiers)
   uint32_t capL, capT, capC, capD;
   __device__ __forceinline__ LayerTab<IDX, SLOT> layer(const EventIO& io, int l) const {
     if constexpr (RING) {
@@ -209,53 +212,93 @@ struct FindScal {
   float z[kLayers];              // plane positions
 };
 
-// Staging of plane l.  RING tiers: the coordinates, bucket order and bucket
-// starts of plane l are loaded into registers at the start of step l+1
-// (issue) and stored into the ring table late in that step (commit), once
-// the seeds of step l+1 no longer read the slot's previous plane (l+3), so
-// the global-memory latency overlaps most of a step.
+// Staging of plane l into the ring (LDS tiers).  The plane's hits are read
+// in key order at the start of step l+1 (issue: coordinates into registers,
+// so the global-memory latency overlaps the step) and counting-sorted into
+// the slot late in that step, once the seeds no longer read the slot's
+// previous plane (l+3):
+//   count   every hit takes its rank inside its azimuth bucket from a packed
+//           16-bit LDS counter (the order inside a bucket is irrelevant:
+//           every use scans whole buckets);
+//   starts  a scan of the bucket counts (by the first wave alone) gives the
+//           slot's bucket starts; the counters are cleared for the next plane;
+//   place   coordinates and local index (the hit's rank in key order) at
+//           bucket start + rank.
+// A barrier must separate count from starts and starts from place; the
+// caller's next barrier publishes the slot.  The used flags and round
+// winners of a plane are cleared at the start of its own step.
 template <int NT, typename IDX, bool RING>
 struct PlanePrefetch {
-  static constexpr int PF = RING ? 4 : 1;            // hits per lane (capL <= 4 NT)
-  static constexpr int PB = (kNB + 1 + NT - 1) / NT;  // bucket starts per lane
+  static constexpr int PF = RING ? 4 : 1;              // hits per lane (capL <= 4 NT)
   float x[PF], y[PF];
-  uint32_t o[PF], bs[PB];
+  uint32_t br[PF];  // bucket | rank << 16
+  uint32_t n = 0;
   __device__ __forceinline__ void issue(const EventIO& io, int l, uint32_t capL) {
     if constexpr (RING) {
-      const uint32_t n = io.lnh[l], base = io.lstart[l];
+      n = io.lnh[l];
+      const uint32_t base = io.lstart[l];
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        if (i < n && i < capL) { x[k] = io.X[base + i]; y[k] = io.Y[base + i]; o[k] = io.order[base + i]; }
-      }
-#pragma unroll
-      for (int k = 0; k < PB; ++k) {
-        const uint32_t b = threadIdx.x + k * NT;
-        if (b <= kNB) bs[k] = io.bst[(uint32_t)l * (kNB + 1) + b];
+        if (i < n && i < capL) { x[k] = io.HX[base + i]; y[k] = io.HY[base + i]; }
       }
     }
   }
-  // Coordinates, local indices and bucket starts only: the used flags and
-  // round winners of a plane are cleared at the start of its own step.  No
-  // barrier: the caller's next barrier publishes the table.
   template <typename MEM>
-  __device__ __forceinline__ void commit(const EventIO& io, int l, const MEM& M) {
+  __device__ __forceinline__ void count(const MEM& M) {
     if constexpr (RING) {
-      const uint32_t n = io.lnh[l];
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < n) {
+          const uint32_t b = bucket_of(pangle(x[k], y[k]), kNB), sh = (b & 1u) << 4;
+          const uint32_t old = atomicAdd(M.cnt + (b >> 1), 1u << sh);
+          br[k] = b | (((old >> sh) & 0xFFFFu) << 16);
+        }
+      }
+    }
+  }
+  // The first wave alone scans the bucket counts (four buckets per lane, a
+  // DPP wave scan), so no extra workgroup barrier is needed: the caller's
+  // next barrier publishes the starts.  Each lane reads its two counter words
+  // before it clears them (a wave's LDS operations complete in order).
+  template <typename MEM>
+  __device__ __forceinline__ void starts(const EventIO& io, int l, const MEM& M) {
+    static_assert(kNB == 4 * kWave, "four buckets per lane of one wave");
+    if constexpr (RING) {
+      if (threadIdx.x >= (uint32_t)kWave) return;
+      IDX* bsd = const_cast<IDX*>(M.layer(io, l).bstart);
+      const uint32_t lane = threadIdx.x;
+      const uint32_t w0 = M.cnt[2 * lane], w1 = M.cnt[2 * lane + 1];
+      const uint32_t c0 = w0 & 0xFFFFu, c1 = w0 >> 16, c2 = w1 & 0xFFFFu, c3 = w1 >> 16;
+      const uint32_t sum = c0 + c1 + c2 + c3;
+      const uint32_t incl = wave_incl_scan(sum);
+      const uint32_t run = incl - sum;
+      bsd[4 * lane] = (IDX)run;
+      bsd[4 * lane + 1] = (IDX)(run + c0);
+      bsd[4 * lane + 2] = (IDX)(run + c0 + c1);
+      bsd[4 * lane + 3] = (IDX)(run + c0 + c1 + c2);
+      if (lane == kWave - 1) bsd[kNB] = (IDX)incl;
+      M.cnt[2 * lane] = 0;
+      M.cnt[2 * lane + 1] = 0;
+    }
+  }
+  template <typename MEM>
+  __device__ __forceinline__ void place(const EventIO& io, int l, const MEM& M) {
+    if constexpr (RING) {
       const auto t = M.layer(io, l);
       float* hx = const_cast<float*>(t.hx);
       float* hy = const_cast<float*>(t.hy);
       IDX* kr = const_cast<IDX*>(t.kr);
-      IDX* bsd = const_cast<IDX*>(t.bstart);
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        if (i < n) { hx[i] = x[k]; hy[i] = y[k]; kr[i] = (IDX)o[k]; }
-      }
-#pragma unroll
-      for (int k = 0; k < PB; ++k) {
-        const uint32_t b = threadIdx.x + k * NT;
-        if (b <= kNB) bsd[b] = (IDX)bs[k];
+        if (i < n) {
+          const uint32_t p = (uint32_t)t.bstart[br[k] & 0xFFFFu] + (br[k] >> 16);
+          hx[p] = x[k];
+          hy[p] = y[k];
+          kr[p] = (IDX)i;
+        }
       }
     }
   }
@@ -327,8 +370,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     return block_scan1<NT, RING>(v, sc.tmp[sbuf], tot);
   };
   PlanePrefetch<NT, IDX, RING> pf;
-  pf.issue(io, kLayers - 1, M.capL);
-  pf.commit(io, kLayers - 1, M);
+  if constexpr (RING) {
+    for (uint32_t w = tid; w < kNB / 2; w += NT) M.cnt[w] = 0;
+    pf.issue(io, kLayers - 1, M.capL);
+    wg_barrier<RING>();
+    pf.count(M);
+    wg_barrier<RING>();
+    pf.starts(io, kLayers - 1, M);
+    wg_barrier<RING>();
+    pf.place(io, kLayers - 1, M);
+  }
   wg_barrier<RING>();
   const auto A = M.T;
   using SLOT = typename CandSlot<RING>::T;
@@ -547,6 +598,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 
     // ---- 2. seeds on planes (l+2, l+1, l) ----
     uint32_t n_new = 0;
+    bool seed_rounds = false;  // conflict rounds ran (their barriers follow the staging's starts)
     const auto T1 = M.layer(io, l < kLayers - 1 ? l + 1 : l);
     const auto T2 = M.layer(io, l < kLayers - 2 ? l + 2 : l);
     uint32_t n1 = 0, n2 = 0;
@@ -698,10 +750,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           });
         }
       }
+      // staging of plane l-1: bucket ranks (published by the next barrier),
+      // then the bucket starts (the slot's starts were last read by the
+      // doublet search, which is over)
+      if (l > 0) pf.count(M);
       wg_barrier<RING>();
+      if (l > 0) pf.starts(io, l - 1, M);
       const uint32_t nc = sc.ncs;
       if (nc > VELO_MAX_CANDIDATES) return 2u;
       if (nc > M.capC) return 1u;
+      seed_rounds = nc > 0;
       if (nc > 0) {
         // greedy independent set by (s, key1, key0, key2)
         auto less_seed = [&](uint32_t i, uint32_t j) {
@@ -782,8 +840,20 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       }
     }
 
-    // stage plane l-1 into the slot of plane l+2, which the seeds no longer read
-    if (l > 0) pf.commit(io, l - 1, M);
+    // place plane l-1 into the slot of plane l+2, whose coordinates and local
+    // indices the seeds no longer read (its round winners stay: they hold the
+    // accepted seeds); steps without seeding count and scan here
+    if (RING && l > 0) {
+      if (l > kLayers - 3) {
+        pf.count(M);
+        wg_barrier<RING>();
+        pf.starts(io, l - 1, M);
+        wg_barrier<RING>();
+      } else if (!seed_rounds) {
+        wg_barrier<RING>();  // publishes the starts (no round barrier did)
+      }
+      pf.place(io, l - 1, M);
+    }
 
     // ---- 3. active table: surviving tracks compacted in place, then new seeds ----
     // Every lane reads its entry before the scan's barrier and writes after it;
@@ -879,29 +949,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 
 // ---------------------------------------------------------------------------
 
-// Azimuth tables of every (event, plane): one 64-lane workgroup per plane,
-// counting sort of the plane's hits by pseudo-angle bucket; at every bucket
-// position the hit's coordinates and local index.  The order inside a bucket
-// is irrelevant: every use scans whole buckets.  Workgroup 0 also clears the
-// lengths of the tiers' hand-over lists, which the tiers read after this kernel.
-__global__ __launch_bounds__(64) void k_phi_tables(const float* __restrict__ X, const float* __restrict__ Y,
-                                                   const uint32_t* __restrict__ hstatus,
-                                                   const uint32_t* __restrict__ lstart,
-                                                   const uint32_t* __restrict__ lnh,
-                                                   const uint64_t* __restrict__ offsets,
-                                                   uint64_t n_pixels, AzOut az,
-                                                   uint32_t* __restrict__ esc_counts) {
-  __shared__ uint32_t cnt[kNB];
-  const uint32_t seg = blockIdx.x, e = seg / kLayers, l = seg % kLayers;
-  if (seg == 0 && threadIdx.x < 3) esc_counts[threadIdx.x] = 0;  // the tiers' hand-over lists
-  const uint64_t b0 = offsets[e], b1 = offsets[e + 1];
-  if (hstatus[e] != 0 || b1 < b0 || b1 > n_pixels) return;
-  azimuth_tables<64>(X, Y, b0 + lstart[27ull * e + l], lnh[seg], seg, cnt, nullptr, az);
+// Lengths of the tiers' hand-over lists, cleared before the first tier runs.
+__global__ __launch_bounds__(64) void k_clear_counts(uint32_t* __restrict__ esc_counts) {
+  if (threadIdx.x < 3) esc_counts[threadIdx.x] = 0;
 }
 
 struct FindArgs {
-  const float* X;  // hit coordinates in bucket order (absolute slots)
+  const float* X;  // hit coordinates in bucket order (absolute slots; workspace tier)
   const float* Y;
+  const float* HX;  // hit coordinates in key order (the hits, absolute slots)
+  const float* HY;
   const uint32_t* hstatus;
   const uint32_t* lstart;
   const uint32_t* lnh;
@@ -919,7 +976,7 @@ struct FindArgs {
 
 __device__ __forceinline__ EventIO event_io(const FindArgs& a, uint32_t e) {
   const uint64_t b = a.offsets[e];
-  return EventIO{a.X + b, a.Y + b, a.lstart + 27ull * e, a.lnh + 26ull * e, a.order + b,
+  return EventIO{a.X + b, a.Y + b, a.HX + b, a.HY + b, a.lstart + 27ull * e, a.lnh + 26ull * e, a.order + b,
                  a.bst + (uint64_t)e * kLayers * (kNB + 1), a.nhits, a.hit_idx, b / 3};
 }
 
@@ -981,12 +1038,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   uint32_t* t_tmatch = reinterpret_cast<uint32_t*>(s_td);
   uint64_t* t_tbest = s_td + CAPT / 2;
   __shared__ uint32_t s_tw[NT >= 512 ? 3 * CAPT + 1 : 1];  // balanced forward search only
+  __shared__ uint32_t s_cnt[kNB / 2];  // bucket counters of the plane being staged
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
   M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
   M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
   M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
+  M.cnt = s_cnt;
   M.T = TrackTab<uint64_t, uint16_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest,
                                      t_tmatch};
   M.cand = nullptr;
@@ -1020,10 +1079,21 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
                                                            const uint32_t* __restrict__ list,
                                                            const uint32_t* __restrict__ list_count) {
   __shared__ FindScal sc;
+  __shared__ uint32_t cnt[kNB];
   const uint32_t count = *list_count;
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const uint32_t e = list[it];
     const uint64_t b = a.offsets[e];
+    // this tier reads the azimuth tables in place: build them for the event
+    if (!event_skipped(a, e)) {
+      const AzOut az{const_cast<uint32_t*>(a.order), const_cast<float*>(a.X), const_cast<float*>(a.Y),
+                     const_cast<uint32_t*>(a.bst)};
+      for (uint32_t l = 0; l < (uint32_t)kLayers; ++l) {
+        azimuth_tables<kGThreads>(a.HX, a.HY, b + a.lstart[27ull * e + l], a.lnh[26ull * e + l],
+                                  26ull * e + l, cnt, sc.tmp[0], az);
+        __syncthreads();  // the next plane clears the counters
+      }
+    }
     const uint32_t ne = (uint32_t)(a.offsets[e + 1] - b);
     FindMem<uint32_t, false> M;
     M.hx = nullptr; M.hy = nullptr; M.kr = nullptr; M.bstart = nullptr;
@@ -1042,6 +1112,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.tw0 = M.tw1 = M.twp = nullptr;
     M.dbl = nullptr;
     M.capD = 0;
+    M.cnt = nullptr;
     if (run_event<kGThreads>(a, P, M, sc, e) && threadIdx.x == 0) {
       // cannot happen: the tables hold every possible hit and track
       a.n_tracks[e] = 0;
@@ -1148,12 +1219,10 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
                            hipStream_t s, const FindCfg& cfg, const hipEvent_t* ev = nullptr) {
   FindWs f;
   find_ws_layout((char*)ws, n_pixels, n_events, &f);
-  FindArgs a{f.xs, f.ys, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
+  FindArgs a{f.xs, f.ys, h->x, h->y, h->status, h->layer_start, h->layer_nhits, f.order, f.bst, offsets,
              n_pixels, t->n_tracks, t->nhits, t->hit_idx, t->status, f.esc_count, f.esc_list};
   const FindConst c = make_find_const(p);
-  hipLaunchKernelGGL(k_phi_tables, dim3(n_events * kLayers), dim3(64), 0, s, h->x, h->y, h->status,
-                     h->layer_start, h->layer_nhits, offsets, n_pixels, AzOut{f.order, f.xs, f.ys, f.bst},
-                     f.esc_counts);
+  hipLaunchKernelGGL(k_clear_counts, dim3(1), dim3(64), 0, s, f.esc_counts);
   const bool ws_mode = cfg.small_grid != 0;
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
   const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
