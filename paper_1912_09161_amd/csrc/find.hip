@@ -1011,7 +1011,7 @@ __device__ __forceinline__ bool run_event(const FindArgs& a, const FindConst& P,
 // LDS tiers: one event per workgroup (list == nullptr) or a persistent loop
 // over a list of events.
 template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t CAPD>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 5 : 1))) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 5 : (NT >= 512 ? 4 : 1)))) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
                                                  const uint32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ list_count,
                                                  uint32_t* __restrict__ steal) {
