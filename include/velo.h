@@ -327,21 +327,35 @@ velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n,
    classifier applies if one was loaded (velo_mlp_load), else the plain cut. */
 typedef struct velo_context velo_context;
 /* The context keeps the geometry (checked here) and the parameters, which
-   velo_reconstruct_batched uses when its params argument is NULL.        */
+   velo_reconstruct_batched uses when its params argument is NULL.  It also
+   creates a side stream (default priority) and two events on the current
+   device, for the forked track-finding tier; if that fails, or on calls made
+   with another device current, the batched form runs unforked.  Destroy
+   waits for the side stream.                                              */
 velo_status velo_context_create(velo_context** ctx, const velo_geometry* geom,
                                 const velo_params* params);
 void velo_context_destroy(velo_context* ctx);
-/* out9 = {how the shapes were chosen (0 not yet, 1 tuned on this context's
+/* out12 = {how the shapes were chosen (0 not yet, 1 tuned on this context's
    first batch, 2 taken from the process-wide tune cache, 3 set by
    velo_context_set_config), clustering grid (0 = one workgroup per segment),
    large-segment grid, track-finding lanes per event, track-finding grid
    (0 = one workgroup per event), fit lanes per event, then the workgroups of
    the three track-finding tiers that take the events the first one hands on
-   (middle 512 lanes, large 1024 lanes, workspace tier)}.  The tuner picks
-   those three as the smallest of {512, 256, 128}, {64, 32, 32}, {16, 8, 8}
-   within 2 % of the best tuning-stream time: a tier's launch keeps its
-   grid's LDS reserved until every workgroup has been placed, which delays
-   other streams when few events escalate.  tuned_ms5 (may be
+   (middle 512 lanes, large 1024 lanes, workspace tier), routing, fork,
+   event order}.
+   The tuner picks those three as the smallest of {512, 256, 128},
+   {64, 32, 32}, {16, 8, 8} within 2 % of the best tuning-stream time: a
+   tier's launch keeps its grid's LDS reserved until every workgroup has been
+   placed, which delays other streams when few events escalate.
+   Routing (one workgroup per event only): 0 none; -1 events with a plane
+   above the first tier's capacity go straight to the middle tier; n > 0 so
+   do events of more than n hits.  Fork 1: the middle tier of the routed
+   events runs on a side stream the context owns, beside the first tier, and
+   joins the caller's stream before the next tier (inside captured graphs
+   too).  Event order 1 (one workgroup per event only): the first tier's
+   workgroups take the events largest first.  The tuner takes order, routing
+   and fork only when they beat neither by 1 %, and the fork only for batches
+   of 8192 events or more.  tuned_ms5 (may be
    NULL) = tuning-stream times of the chosen clustering, track-finding and fit
    shapes, then the best clustering time with one workgroup per segment and
    the best track-finding time with one workgroup per event (zeros when set
@@ -351,17 +365,19 @@ void velo_context_destroy(velo_context* ctx);
    quarter-octave classes), the classifier flag and the parameters: a new
    context whose first batch falls in a cached class takes the shapes from
    there without timing anything.                                           */
-velo_status velo_context_config(const velo_context* ctx, int32_t* out9, float* tuned_ms5);
+velo_status velo_context_config(const velo_context* ctx, int32_t* out12, float* tuned_ms5);
 /* Fix the launch shapes of a context instead of tuning them (for callers that
    know their workload, and for tests that run every shape):
-   in8 = {clustering grid 0..65536 (0 = one workgroup per segment),
+   in11 = {clustering grid 0..65536 (0 = one workgroup per segment),
    large-segment grid 1..65536, track-finding lanes 128 or 256, track-finding
    grid 0..65536 (0 = one workgroup per event), fit lanes 64, 128 or 256,
    middle-tier workgroups 1..512, large-tier workgroups 1..256,
-   workspace-tier workgroups 1..128}.
+   workspace-tier workgroups 1..128, routing -1..2^31-1 (non-zero only with
+   track-finding grid 0), fork 0 or 1 (1 only with routing), event order 0
+   or 1 (1 only with track-finding grid 0)}.
    Other values return VELO_ERR_ARG and leave the context unchanged.  Drops
    the context's captured graphs; results do not depend on the shapes.      */
-velo_status velo_context_set_config(velo_context* ctx, const int32_t* in8);
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in11);
 size_t velo_batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
 velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels,
                                      const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,

@@ -162,6 +162,15 @@ struct BatchedCfg {
   uint32_t find_grid;    // persistent track-finding workgroups (0: one per event)
   int fit_threads;
   uint32_t esc_grid[3];  // workgroups of the middle, large and workspace track-finding tiers
+  uint32_t route_hits;   // events routed past the small track-finding tier (0: none; find_grid == 0)
+  uint32_t fork;         // routed events' middle tier on the side stream, beside the small tier
+  uint32_t find_order;   // find_grid == 0: workgroups take the events largest first
+};
+
+// The side stream and the two events of a fork (side == null: no fork).
+struct Fork {
+  hipStream_t side;
+  hipEvent_t fork_ev, join_ev;
 };
 
 size_t batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events) {
@@ -187,14 +196,14 @@ struct BatchedCall {
 
 // ordering + the three stages with the given launch shapes
 static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hipStream_t s,
-                                  int stages = 7) {
+                                  const Fork& fk, int stages = 7) {
   const size_t main_ws = c.ws_bytes - order_ws_layout(nullptr, c.n_events, nullptr);
   OrderWs ow;
   order_ws_layout((char*)c.ws + main_ws, c.n_events, &ow);
   if (stages & 1) {
     // clearing (only the persistent kernels and the size orders use the
     // counters), validation, size ordering, clustering
-    const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid ? kOrderEvents : 0u);
+    const uint32_t mode = (k.small_grid ? kOrderSegs : 0u) | (k.find_grid || k.find_order ? kOrderEvents : 0u);
     if (mode)
       hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, ow.counters, 16u + kSegClasses + kEvClasses);
     launch_validate(c.px, c.offsets, c.n_events, c.n_pixels, c.hits.status, c.hits.layer_start,
@@ -215,8 +224,10 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
   if (stages & 2) {
     if (k.find_grid)  // work-stealing counters of the persistent track-finding tiers
       hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, ow.counters + 2, 3u);
+    const bool fork = k.fork && k.route_hits && fk.side;
     const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2,
-                     {k.esc_grid[0], k.esc_grid[1], k.esc_grid[2]}};
+                     {k.esc_grid[0], k.esc_grid[1], k.esc_grid[2]}, k.find_grid ? 0u : k.route_hits,
+                     fork ? fk.side : nullptr, fk.fork_ev, fk.join_ev, k.find_grid ? 0u : k.find_order};
     hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
                                    c.ws, s, fc);
     if (e != hipSuccess) return e;
@@ -247,7 +258,11 @@ struct velo_context {
   velo_params params{};  // used when a call passes no parameters
   bool tuned = false;
   int source = 0;  // how cfg was chosen: 1 tuned here, 2 tune cache, 3 set by the caller
-  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128, {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks}};
+  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128, {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks}, 0, 0, 0};
+  // side stream and events of the forked track-finding tier, made with the
+  // context on side_dev (calls on another device run unforked)
+  velo::Fork fork{nullptr, nullptr, nullptr};
+  int side_dev = -1;
   float tuned_ms[5] = {0, 0, 0, 0, 0};
   // captured graphs of recent call shapes (buffers, sizes, parameters, stream)
   static constexpr int kGraphs = 32;
@@ -282,8 +297,8 @@ void drop_graphs(velo_context* ctx) {
 }
 
 // time one stage (min of `reps` runs) with events on the stream
-hipError_t time_stage(const velo::BatchedCall& c, const velo::BatchedCfg& k, int stage, hipStream_t s,
-                      int reps, float* ms) {
+hipError_t time_stage(const velo::BatchedCall& c, const velo::BatchedCfg& k, const velo::Fork& fk, int stage,
+                      hipStream_t s, int reps, float* ms) {
   hipEvent_t a, b;
   hipError_t e = hipEventCreate(&a);
   if (e != hipSuccess) return e;
@@ -292,7 +307,7 @@ hipError_t time_stage(const velo::BatchedCall& c, const velo::BatchedCfg& k, int
   float best = 1e30f;
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(a, s);
-    if (e == hipSuccess) e = velo::enqueue_batched(c, k, s, stage);
+    if (e == hipSuccess) e = velo::enqueue_batched(c, k, s, fk, stage);
     if (e == hipSuccess) e = hipEventRecord(b, s);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0;
@@ -318,8 +333,9 @@ constexpr float kPersistentGain = 0.85f;
 
 // Pick the launch shapes stage by stage on the live batch: clustering first
 // (its output feeds the next stage), then track finding, then the fit.
-static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t s) {
+static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t s, const Fork& fk) {
   BatchedCfg best = ctx->cfg;
+  best.find_order = 1;  // the clustering stage builds the event order the track-finding candidates use
   float t;
   hipError_t e;
   // clustering: one workgroup per segment, or persistent grids of several
@@ -337,7 +353,7 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
       for (int j = 0; j < kNM; ++j) {
         k.small_grid = smalls[i];
         k.mid_grid = mids[j];
-        if ((e = time_stage(c, k, 1, s, 3, &t)) != hipSuccess) return e;
+        if ((e = time_stage(c, k, fk, 1, s, 3, &t)) != hipSuccess) return e;
         tm[i][j] = t;
         const int p = smalls[i] != 0;
         if (t < bt[p]) { bt[p] = t; pick[p] = k; }
@@ -351,10 +367,11 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
           if (tm[i][j] <= 1.02f * bt[p]) best.mid_grid = mids[j];
     ctx->tuned_ms[0] = bt[p];
     ctx->tuned_ms[3] = bt[0];
-    if ((e = enqueue_batched(c, best, s, 1)) != hipSuccess) return e;
+    if ((e = enqueue_batched(c, best, s, fk, 1)) != hipSuccess) return e;
   }
   // track finding: lanes per event x (one workgroup per event | persistent grid)
   {
+    best.find_order = 0;
     const int threads[] = {128, 256};
     const uint32_t grids[] = {0, 512, 768, 1024, 1536};
     float bt[2] = {1e30f, 1e30f};  // one workgroup per event, persistent
@@ -363,7 +380,7 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
       for (uint32_t g : grids) {
         k.find_threads = nt;
         k.find_grid = g;
-        if ((e = time_stage(c, k, 2, s, 3, &t)) != hipSuccess) return e;
+        if ((e = time_stage(c, k, fk, 2, s, 3, &t)) != hipSuccess) return e;
         const int p = g != 0;
         if (t < bt[p]) { bt[p] = t; pick[p] = k; }
       }
@@ -382,7 +399,7 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     BatchedCfg k2 = best;
     for (int i = 0; i < 3; ++i) {
       for (int j = 0; j < 3; ++j) k2.esc_grid[j] = esc[i][j];
-      if ((e = time_stage(c, k2, 2, s, 3, &et[i])) != hipSuccess) return e;
+      if ((e = time_stage(c, k2, fk, 2, s, 3, &et[i])) != hipSuccess) return e;
     }
     float tbest = et[0];
     for (int i = 1; i < 3; ++i) tbest = et[i] < tbest ? et[i] : tbest;
@@ -390,7 +407,39 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     for (int i = 0; i < 3; ++i)
       if (et[i] <= 1.02f * tbest) pe = i;
     for (int j = 0; j < 3; ++j) best.esc_grid[j] = esc[pe][j];
-    if ((e = enqueue_batched(c, best, s, 2)) != hipSuccess) return e;
+    // one workgroup per event: the events largest first (a shorter tail),
+    // and routing: events the small tier would hand on after part of their
+    // work (a plane above its capacity, or more hits than a bound) go straight
+    // to the middle tier, which, with a fork, runs beside the small tier.
+    // Taken only when it beats the plain order by 1 % on the tuning stream;
+    // the fork only for batches that fill the GPU on their own (beside other
+    // streams a second stream mostly competes for the same CUs).  The tier
+    // grids are tried again at full size, which the routed events may need.
+    if (best.find_grid == 0) {
+      constexpr int kNR = 6;
+      const uint32_t ro[kNR][3] = {// order, route, fork
+                                   {1, 0, 0}, {0, 0xFFFFFFFFu, 0}, {1, 0xFFFFFFFFu, 0},
+                                   {0, 0xFFFFFFFFu, 1}, {1, 0xFFFFFFFFu, 1}, {1, 4200u, 1}};
+      const bool can_fork = c.n_events >= 8192 && fk.side;
+      float rbest = tbest;
+      BatchedCfg k3 = best, rpick = best;
+      for (int i = 0; i < kNR; ++i) {
+        if (ro[i][2] && !can_fork) continue;
+        for (int g = 0; g < (pe == 0 ? 1 : 2); ++g) {
+          k3.find_order = ro[i][0];
+          k3.route_hits = ro[i][1];
+          k3.fork = ro[i][2];
+          for (int j = 0; j < 3; ++j) k3.esc_grid[j] = esc[g == 0 ? pe : 0][j];
+          if ((e = time_stage(c, k3, fk, 2, s, 3, &t)) != hipSuccess) return e;
+          if (t < rbest) { rbest = t; rpick = k3; }
+        }
+      }
+      if (rbest < 0.99f * tbest) {
+        best = rpick;
+        ctx->tuned_ms[1] = rbest;
+      }
+    }
+    if ((e = enqueue_batched(c, best, s, fk, 2)) != hipSuccess) return e;
   }
   // fit: lanes per event
   {
@@ -399,7 +448,7 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     BatchedCfg k = best;
     for (int nt : threads) {
       k.fit_threads = nt;
-      if ((e = time_stage(c, k, 4, s, 3, &t)) != hipSuccess) return e;
+      if ((e = time_stage(c, k, fk, 4, s, 3, &t)) != hipSuccess) return e;
       if (t < bt) { bt = t; best.fit_threads = nt; }
     }
     ctx->tuned_ms[2] = bt;

@@ -949,9 +949,10 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
 
 // ---------------------------------------------------------------------------
 
-// Lengths of the tiers' hand-over lists, cleared before the first tier runs.
+// Lengths of the tiers' hand-over lists (and of the routing lists), cleared
+// before the first tier runs.
 __global__ __launch_bounds__(64) void k_clear_counts(uint32_t* __restrict__ esc_counts) {
-  if (threadIdx.x < 3) esc_counts[threadIdx.x] = 0;
+  if (threadIdx.x < 5) esc_counts[threadIdx.x] = 0;
 }
 
 struct FindArgs {
@@ -1136,8 +1137,10 @@ constexpr uint32_t kLCapL = 1024, kLCapT = 1024, kLCapC = 2048, kLCapD = 4096, k
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct FindWs {
-  uint32_t* esc_counts;  // [3] hand-over list lengths: small -> middle -> large -> workspace tier
+  uint32_t* esc_counts;  // [5] list lengths: small -> middle -> large -> workspace tier hand-overs,
+                         // then the routed events and the small tier's events (routing)
   uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *esc3_count, *esc3_list, *order, *bst;
+  uint32_t *route_count, *route_list, *small_count, *small_list;
   float *xs, *ys;
   GlobalTabs g;
 };
@@ -1148,13 +1151,17 @@ static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, Find
   auto take = [&](size_t bytes) { char* r = w ? w + o : nullptr; o += up256(bytes); return r; };
   const uint64_t nt = n_pixels / 3 + 1;
   FindWs f;
-  f.esc_counts = (uint32_t*)take(12);
+  f.esc_counts = (uint32_t*)take(20);
   f.esc_count = f.esc_counts;
   f.esc2_count = f.esc_counts ? f.esc_counts + 1 : nullptr;
   f.esc3_count = f.esc_counts ? f.esc_counts + 2 : nullptr;
+  f.route_count = f.esc_counts ? f.esc_counts + 3 : nullptr;
+  f.small_count = f.esc_counts ? f.esc_counts + 4 : nullptr;
   f.esc_list = (uint32_t*)take(4ull * n_events);
   f.esc2_list = (uint32_t*)take(4ull * n_events);
   f.esc3_list = (uint32_t*)take(4ull * n_events);
+  f.route_list = (uint32_t*)take(4ull * n_events);
+  f.small_list = (uint32_t*)take(4ull * n_events);
   f.order = (uint32_t*)take(4ull * n_pixels);
   f.xs = (float*)take(4ull * n_pixels);
   f.ys = (float*)take(4ull * n_pixels);
@@ -1209,9 +1216,50 @@ struct FindCfg {
   // every one of them has been placed and found the list empty, so a small
   // grid frees the GPU sooner when few events escalate.
   uint32_t esc_grid[3];
+  // Routing (batched form; needs small_grid == 0): events with a plane above
+  // the small tier's capacity, or with more than route_hits hits, go straight
+  // to the middle tier instead of being handed on by the small tier, possibly
+  // after part of their work (0: no routing).  side (may be null): the middle
+  // tier of the routed events then runs on this stream, forked from `s` by
+  // fork_ev and joined back by join_ev, beside the small tier.
+  uint32_t route_hits;
+  hipStream_t side;
+  hipEvent_t fork_ev, join_ev;
+  // small_grid == 0: the small tier (and routing) takes the events in
+  // ev_order (largest first) instead of index order
+  uint32_t ordered;
 };
 
 static uint32_t tier_grid(uint32_t want, uint32_t full) { return want == 0 || want > full ? full : want; }
+
+// Routing (batched form): one lane per event (in `order` when given, so that
+// the lists keep it within each wave).  A skipped event gets its
+// empty outputs here (no tier sees it); an event with a plane above the small
+// tier's capacity or more than route_hits hits goes to the routed list, the
+// others to the small tier's list.
+__global__ __launch_bounds__(256) void k_route(FindArgs a, uint32_t n_events, uint32_t route_hits,
+                                               const uint32_t* __restrict__ order,
+                                               uint32_t* __restrict__ route_count,
+                                               uint32_t* __restrict__ route_list,
+                                               uint32_t* __restrict__ small_count,
+                                               uint32_t* __restrict__ small_list) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n_events) return;
+  const uint32_t e = order ? order[i] : i;
+  if (event_skipped(a, e)) {
+    a.n_tracks[e] = 0;
+    a.tstatus[e] = 0;
+    return;
+  }
+  uint32_t mx = 0, tot = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const uint32_t v = a.lnh[26ull * e + l];
+    mx = v > mx ? v : mx;
+    tot += v;
+  }
+  if (mx > kSCapL || tot > route_hits) route_list[atomicAdd(route_count, 1u)] = e;
+  else small_list[atomicAdd(small_count, 1u)] = e;
+}
 
 // ev (may be null): events recorded just before and after the per-event kernel
 hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t n_events,
@@ -1223,22 +1271,49 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
              n_pixels, t->n_tracks, t->nhits, t->hit_idx, t->status, f.esc_count, f.esc_list};
   const FindConst c = make_find_const(p);
   hipLaunchKernelGGL(k_clear_counts, dim3(1), dim3(64), 0, s, f.esc_counts);
+  const bool route = cfg.route_hits != 0 && cfg.small_grid == 0;
   const bool ws_mode = cfg.small_grid != 0;
   const dim3 grid(ws_mode ? cfg.small_grid : n_events);
-  const uint32_t* order = ws_mode ? cfg.ev_order : nullptr;
+  const uint32_t* order = ws_mode || cfg.ordered ? cfg.ev_order : nullptr;
   uint32_t* steal = ws_mode ? cfg.counters : nullptr;
-  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
-  if (cfg.small_threads == 128)
-    hipLaunchKernelGGL((k_find_lds<128, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(128), 0, s, a, c,
-                       n_events, order, (const uint32_t*)nullptr, steal);
-  else
-    hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(kSThreads),
-                       0, s, a, c, n_events, order, (const uint32_t*)nullptr, steal);
-  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
   FindArgs a2 = a;
   a2.esc_count = f.esc2_count;
   a2.esc_list = f.esc2_list;
-  hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), dim3(tier_grid(cfg.esc_grid[0], kMBlocks)),
+  const dim3 mgrid(tier_grid(cfg.esc_grid[0], kMBlocks));
+  if (route) {
+    hipLaunchKernelGGL(k_route, dim3((n_events + 255) / 256), dim3(256), 0, s, a, n_events, cfg.route_hits,
+                       order, f.route_count, f.route_list, f.small_count, f.small_list);
+    // the middle tier on the routed events: beside the small tier on the side
+    // stream, or before it
+    hipStream_t ms = s;
+    if (cfg.side) {
+      hipError_t e = hipEventRecord(cfg.fork_ev, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(cfg.side, cfg.fork_ev, 0);
+      if (e != hipSuccess) return e;
+      ms = cfg.side;
+    }
+    hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), mgrid, dim3(kMThreads), 0, ms,
+                       a2, c, n_events, f.route_list, f.route_count, (uint32_t*)nullptr);
+    if (cfg.side) {
+      hipError_t e = hipEventRecord(cfg.join_ev, cfg.side);
+      if (e != hipSuccess) return e;
+    }
+  }
+  const uint32_t* slist = route ? f.small_list : order;
+  const uint32_t* scount = route ? f.small_count : (const uint32_t*)nullptr;
+  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
+  if (cfg.small_threads == 128)
+    hipLaunchKernelGGL((k_find_lds<128, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(128), 0, s, a, c,
+                       n_events, slist, scount, steal);
+  else
+    hipLaunchKernelGGL((k_find_lds<kSThreads, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(kSThreads),
+                       0, s, a, c, n_events, slist, scount, steal);
+  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
+  if (route && cfg.side) {
+    hipError_t e = hipStreamWaitEvent(s, cfg.join_ev, 0);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_find_lds<kMThreads, kMCapL, kMCapT, kMCapC, kMCapD>), mgrid,
                      dim3(kMThreads), 0, s, a2, c, n_events, f.esc_list, f.esc_count,
                      ws_mode ? cfg.counters + 1 : (uint32_t*)nullptr);
   FindArgs a3 = a;
@@ -1256,7 +1331,7 @@ hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_e
                        uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
                        hipStream_t s) {
   return launch_find_cfg(h, offsets, n_events, n_pixels, p, t, ws, s,
-                         FindCfg{kSThreads, 0, nullptr, nullptr, {0, 0, 0}});
+                         FindCfg{kSThreads, 0, nullptr, nullptr, {0, 0, 0}, 0, nullptr, nullptr, nullptr, 0});
 }
 
 }  // namespace velo

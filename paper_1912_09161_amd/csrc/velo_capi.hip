@@ -365,6 +365,23 @@ velo_status velo_context_create(velo_context** ctx, const velo_geometry* geom,
   if (!ctx || !geometry_ok(geom) || !params_ok(params)) return VELO_ERR_ARG;
   velo_context* c = new velo_context();
   c->params = *params;
+  // side stream of the forked track-finding tier (default priority); without
+  // it the batched form runs unforked
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipStreamCreateWithFlags(&c->fork.side, hipStreamNonBlocking) == hipSuccess) {
+    if (hipEventCreateWithFlags(&c->fork.fork_ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&c->fork.join_ev, hipEventDisableTiming) == hipSuccess) {
+      c->side_dev = dev;
+    } else {
+      if (c->fork.fork_ev) (void)hipEventDestroy(c->fork.fork_ev);
+      (void)hipStreamDestroy(c->fork.side);
+      c->fork = velo::Fork{nullptr, nullptr, nullptr};
+    }
+  } else {
+    c->fork.side = nullptr;
+  }
+  (void)hipGetLastError();
   *ctx = c;
   return VELO_OK;
 }
@@ -375,20 +392,31 @@ void velo_context_destroy(velo_context* ctx) {
   void* bufs[] = {ctx->net, ctx->adam_m, ctx->adam_v, ctx->grad, ctx->loss, ctx->mlp_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  if (ctx->fork.side) {
+    (void)hipStreamSynchronize(ctx->fork.side);
+    (void)hipEventDestroy(ctx->fork.fork_ev);
+    (void)hipEventDestroy(ctx->fork.join_ev);
+    (void)hipStreamDestroy(ctx->fork.side);
+  }
   delete ctx;
 }
 
-velo_status velo_context_set_config(velo_context* ctx, const int32_t* in8) {
-  if (!ctx || !in8) return VELO_ERR_ARG;
-  const int32_t cg = in8[0], mg = in8[1], ft = in8[2], fg = in8[3], fit = in8[4];
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in11) {
+  if (!ctx || !in11) return VELO_ERR_ARG;
+  const int32_t cg = in11[0], mg = in11[1], ft = in11[2], fg = in11[3], fit = in11[4];
+  const int32_t route = in11[8], fork = in11[9], order = in11[10];
   if (cg < 0 || cg > 65536 || mg < 1 || mg > 65536 || (ft != 128 && ft != 256) || fg < 0 ||
       fg > 65536 || (fit != 64 && fit != 128 && fit != 256))
     return VELO_ERR_ARG;
+  if (route < -1 || (route != 0 && fg != 0) || (fork != 0 && fork != 1) || (fork && !route) ||
+      (order != 0 && order != 1) || (order && fg != 0))
+    return VELO_ERR_ARG;
   const uint32_t full[3] = {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks};
   for (int i = 0; i < 3; ++i)
-    if (in8[5 + i] < 1 || (uint32_t)in8[5 + i] > full[i]) return VELO_ERR_ARG;
+    if (in11[5 + i] < 1 || (uint32_t)in11[5 + i] > full[i]) return VELO_ERR_ARG;
   ctx->cfg = velo::BatchedCfg{(uint32_t)cg, (uint32_t)mg, ft, (uint32_t)fg, fit,
-                              {(uint32_t)in8[5], (uint32_t)in8[6], (uint32_t)in8[7]}};
+                              {(uint32_t)in11[5], (uint32_t)in11[6], (uint32_t)in11[7]},
+                              route == -1 ? 0xFFFFFFFFu : (uint32_t)route, (uint32_t)fork, (uint32_t)order};
   ctx->tuned = true;
   ctx->source = 3;
   for (int i = 0; i < 5; ++i) ctx->tuned_ms[i] = 0.0f;
@@ -396,15 +424,18 @@ velo_status velo_context_set_config(velo_context* ctx, const int32_t* in8) {
   return VELO_OK;
 }
 
-velo_status velo_context_config(const velo_context* ctx, int32_t* out9, float* tuned_ms5) {
-  if (!ctx || !out9) return VELO_ERR_ARG;
-  out9[0] = ctx->tuned ? ctx->source : 0;
-  out9[1] = (int32_t)ctx->cfg.small_grid;
-  out9[2] = (int32_t)ctx->cfg.mid_grid;
-  out9[3] = ctx->cfg.find_threads;
-  out9[4] = (int32_t)ctx->cfg.find_grid;
-  out9[5] = ctx->cfg.fit_threads;
-  for (int i = 0; i < 3; ++i) out9[6 + i] = (int32_t)ctx->cfg.esc_grid[i];
+velo_status velo_context_config(const velo_context* ctx, int32_t* out12, float* tuned_ms5) {
+  if (!ctx || !out12) return VELO_ERR_ARG;
+  out12[0] = ctx->tuned ? ctx->source : 0;
+  out12[1] = (int32_t)ctx->cfg.small_grid;
+  out12[2] = (int32_t)ctx->cfg.mid_grid;
+  out12[3] = ctx->cfg.find_threads;
+  out12[4] = (int32_t)ctx->cfg.find_grid;
+  out12[5] = ctx->cfg.fit_threads;
+  for (int i = 0; i < 3; ++i) out12[6 + i] = (int32_t)ctx->cfg.esc_grid[i];
+  out12[9] = ctx->cfg.route_hits == 0xFFFFFFFFu ? -1 : (int32_t)ctx->cfg.route_hits;
+  out12[10] = (int32_t)ctx->cfg.fork;
+  out12[11] = (int32_t)ctx->cfg.find_order;
   if (tuned_ms5)
     for (int i = 0; i < 5; ++i) tuned_ms5[i] = ctx->tuned_ms[i];
   return VELO_OK;
@@ -451,7 +482,11 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
   // current shapes (no tuning, which synchronises, and no graph of our own)
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (stream != nullptr && hipStreamIsCapturing(stream, &cs) != hipSuccess) return VELO_ERR_HIP;
-  if (cs != hipStreamCaptureStatusNone) return hip_status(velo::enqueue_batched(c, ctx->cfg, stream));
+  // the fork's side stream serves calls on the device the context was made on
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return VELO_ERR_HIP;
+  const velo::Fork fk = dev == ctx->side_dev ? ctx->fork : velo::Fork{nullptr, nullptr, nullptr};
+  if (cs != hipStreamCaptureStatusNone) return hip_status(velo::enqueue_batched(c, ctx->cfg, stream, fk));
   if (!ctx->tuned) {
     TuneKey k;
     const bool keyed = tune_key(c, &k);
@@ -459,14 +494,14 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
       ctx->tuned = true;
       ctx->source = 2;
     } else {
-      if ((e = velo::autotune(ctx, c, stream)) != hipSuccess) return VELO_ERR_HIP;
+      if ((e = velo::autotune(ctx, c, stream, fk)) != hipSuccess) return VELO_ERR_HIP;
       ctx->source = 1;
       if (keyed) tune_store(k, ctx->cfg, ctx->tuned_ms);
     }
     drop_graphs(ctx);
   }
   if (stream == nullptr)  // the legacy default stream cannot be captured
-    return hip_status(velo::enqueue_batched(c, ctx->cfg, stream));
+    return hip_status(velo::enqueue_batched(c, ctx->cfg, stream, fk));
   ctx->clock++;
   for (int i = 0; i < ctx->n_graphs; ++i) {
     velo_context::Entry& g = ctx->graphs[i];
@@ -493,7 +528,7 @@ velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels
     ctx->n_graphs--;
     return VELO_ERR_HIP;
   }
-  const hipError_t le = velo::enqueue_batched(c, ctx->cfg, stream);
+  const hipError_t le = velo::enqueue_batched(c, ctx->cfg, stream, fk);
   e = hipStreamEndCapture(stream, &g.graph);
   if (le == hipSuccess && e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
   if (le != hipSuccess || e != hipSuccess) {

@@ -68,9 +68,44 @@ def test_batched_equals_plain_and_replays(name, n, xl):
     ctx.close()
 
 
-def test_batched_inside_a_caller_graph():
-    """A caller captures the (already tuned) batched call into its own graph:
-    the call only enqueues; every replay equals the plain form."""
+FORKED = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
+              tier_grids=(16, 8, 8), route_hits=3000, fork=True, find_order=True)
+
+
+@pytest.mark.parametrize("route", [0, 3000, 1])
+def test_forked_routing_replays(route):
+    """Events routed past the first track-finding tier, their middle tier on
+    the context's side stream: the context's own graph (fork and join inside
+    it) replayed, with eager work between replays, equals the plain form."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    b = generate("stress", 120, first_event=40, workers=8)
+    P = velo.default_params(x_over_x0=2.38e-3)
+    ref = plain(b, P)
+    px, off = to_dev(b.pixels, b.offsets)
+    ctx = velo.Context()
+    ctx.set_config(**dict(FORKED, route_hits=route, fork=route != 0, find_order=route != 1))
+    stream = torch.cuda.Stream()
+    bufs = None
+    for r in range(4):
+        if bufs is not None:
+            for k in ("n_tracks", "nhits"):
+                bufs["tracks"][k].fill_(9)
+            torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            bufs = ctx.reconstruct(px, off, params=P, bufs=bufs, stream=stream)
+        stream.synchronize()
+        _ = (px.to(torch.int64).sum() + r).item()
+        same(host(bufs), ref, b)
+    ctx.close()
+
+
+@pytest.mark.parametrize("forked", [False, True])
+def test_batched_inside_a_caller_graph(forked):
+    """A caller captures the (already tuned, or fixed with the routed tier
+    forked onto the side stream) batched call into its own graph: the call
+    only enqueues; every replay equals the plain form."""
     import torch
 
     import paper_1912_09161_amd as velo
@@ -79,6 +114,8 @@ def test_batched_inside_a_caller_graph():
     ref = plain(b, P)
     px, off = to_dev(b.pixels, b.offsets)
     ctx = velo.Context()
+    if forked:
+        ctx.set_config(**FORKED)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         bufs = ctx.reconstruct(px, off, params=P, stream=stream)  # tunes eagerly

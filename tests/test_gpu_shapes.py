@@ -8,7 +8,10 @@ element: clustering one workgroup per segment or persistent grids of 1024 to
 8192 workgroups (with 64 to 1024 large-segment workgroups), track finding
 with 128 or 256 lanes per event, one workgroup per event or persistent grids
 of 512 to 1536, the fit with 64 to 256 lanes, the tiers that take the
-escalated events with grids from their full size down to one workgroup.
+escalated events with grids from their full size down to one workgroup,
+events taken largest first by the first tier, events routed past it (by
+plane capacity, by hits, all of them) with and without the fork onto the
+context's side stream.
 Events of uneven occupancy and high-occupancy events (where the larger
 track-finding tiers run).
 """
@@ -24,6 +27,11 @@ CLUSTER = [(cg, mg) for cg in (0, 1024, 2048, 4096, 8192) for mg in (64, 256, 51
 FIND = [(nt, g) for nt in (128, 256) for g in (0, 512, 768, 1024, 1536)]
 FIT = [64, 128, 256]
 TIERS = [(64, 32, 32), (16, 8, 8), (1, 1, 1)]
+# first tier largest event first; routing past the first tier: by plane
+# capacity only, by hits, every event; unforked and forked, with full and with
+# one-workgroup tier grids
+ROUTE = [(0, False, True), (-1, False, False), (3000, False, True), (1, False, False), (3000, True, False),
+         (1, True, True), (-1, True, True)]
 BASE = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
             tier_grids=(512, 256, 128))
 
@@ -33,6 +41,8 @@ def shapes():
     out += [dict(BASE, find_threads=nt, find_grid=g) for nt, g in FIND]
     out += [dict(BASE, fit_threads=f) for f in FIT]
     out += [dict(BASE, tier_grids=t) for t in TIERS]
+    out += [dict(BASE, route_hits=r, fork=f, find_order=o) for r, f, o in ROUTE]
+    out += [dict(BASE, find_threads=128, route_hits=3000, fork=True, find_order=True, tier_grids=(1, 1, 1))]
     # all persistent at once
     out.append(dict(cluster_grid=2048, mid_grid=512, find_threads=256, find_grid=1024, fit_threads=128,
                     tier_grids=(16, 8, 8)))
@@ -64,6 +74,8 @@ def test_every_launch_shape_equals_oracle(orc, name, n, xl):
         cfg = ctx.config()
         assert cfg["source"] == "set" and cfg["find_grid"] == sh["find_grid"]
         assert cfg["tier_grids"] == list(sh["tier_grids"])
+        assert cfg["route_hits"] == sh.get("route_hits", 0) and cfg["fork"] == sh.get("fork", False)
+        assert cfg["find_order"] == sh.get("find_order", False)
         if bufs is not None:  # stale outputs of the previous shape must be overwritten
             for k in ("n_tracks", "nhits"):
                 bufs["tracks"][k].fill_(7)
@@ -82,7 +94,9 @@ def test_set_config_rejects_bad_shapes():
     ctx = velo.Context()
     for bad in (dict(find_threads=192), dict(fit_threads=32), dict(mid_grid=0), dict(cluster_grid=-1),
                 dict(find_grid=70000), dict(tier_grids=(0, 8, 8)), dict(tier_grids=(513, 8, 8)),
-                dict(tier_grids=(16, 257, 8)), dict(tier_grids=(16, 8, 129))):
+                dict(tier_grids=(16, 257, 8)), dict(tier_grids=(16, 8, 129)),
+                dict(route_hits=-2), dict(route_hits=3000, find_grid=512), dict(fork=True),
+                dict(route_hits=1, fork=2), dict(find_order=True, find_grid=512), dict(find_order=2)):
         with pytest.raises(velo.VeloError):
             ctx.set_config(**dict(BASE, **bad))
     assert ctx.config()["source"] == "untuned"
