@@ -353,9 +353,11 @@ void velo_context_destroy(velo_context* ctx);
    events runs on a side stream the context owns, beside the first tier, and
    joins the caller's stream before the next tier (inside captured graphs
    too).  Event order 1 (one workgroup per event only): the first tier's
-   workgroups take the events largest first.  The tuner takes order, routing
-   and fork only when they beat neither by 1 %, and the fork only for batches
-   of 8192 events or more.  tuned_ms5 (may be
+   workgroups take the events largest first.  The tuner tries order,
+   routing by plane capacity and fork only for batches of 8192 events or
+   more (a smaller batch starts all its events at once, and beside other
+   streams the extra kernels cost more than they save) and takes them only
+   when they beat none of them by 1 %.  tuned_ms5 (may be
    NULL) = tuning-stream times of the chosen clustering, track-finding and fit
    shapes, then the best clustering time with one workgroup per segment and
    the best track-finding time with one workgroup per event (zeros when set

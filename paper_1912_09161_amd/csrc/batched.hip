@@ -407,20 +407,21 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     for (int i = 0; i < 3; ++i)
       if (et[i] <= 1.02f * tbest) pe = i;
     for (int j = 0; j < 3; ++j) best.esc_grid[j] = esc[pe][j];
-    // one workgroup per event: the events largest first (a shorter tail),
-    // and routing: events the small tier would hand on after part of their
-    // work (a plane above its capacity, or more hits than a bound) go straight
-    // to the middle tier, which, with a fork, runs beside the small tier.
-    // Taken only when it beats the plain order by 1 % on the tuning stream;
-    // the fork only for batches that fill the GPU on their own (beside other
-    // streams a second stream mostly competes for the same CUs).  The tier
-    // grids are tried again at full size, which the routed events may need.
-    if (best.find_grid == 0) {
-      constexpr int kNR = 6;
+    // one workgroup per event, batches that fill the GPU on their own (at
+    // least 8192 events; a smaller batch starts all its events at once, and
+    // beside other streams the extra kernels and launches cost more than they
+    // save): the events largest first (a shorter tail), and routing: events
+    // the small tier would hand on after part of their work (a plane above
+    // its capacity) go straight to the middle
+    // tier, which, with a fork, runs beside the small tier.  Taken only when
+    // they beat the plain order by 1 % on the tuning stream.  The tier grids
+    // are tried again at full size, which the routed events may need.
+    if (best.find_grid == 0 && c.n_events >= 8192) {
+      constexpr int kNR = 5;
       const uint32_t ro[kNR][3] = {// order, route, fork
                                    {1, 0, 0}, {0, 0xFFFFFFFFu, 0}, {1, 0xFFFFFFFFu, 0},
-                                   {0, 0xFFFFFFFFu, 1}, {1, 0xFFFFFFFFu, 1}, {1, 4200u, 1}};
-      const bool can_fork = c.n_events >= 8192 && fk.side;
+                                   {0, 0xFFFFFFFFu, 1}, {1, 0xFFFFFFFFu, 1}};
+      const bool can_fork = fk.side != nullptr;
       float rbest = tbest;
       BatchedCfg k3 = best, rpick = best;
       for (int i = 0; i < kNR; ++i) {
