@@ -45,25 +45,30 @@ struct FindConst {
 
 
 // One plane, indexed by bucket position p.  The hit's local index (rank of
-// its key in the plane, the order of its event-relative slot) is kr[p].
+// its key in the plane, the order of its event-relative slot) is kr[p].  The
+// LDS tiers (64-bit round winners) interleave x and y, so that one 8-byte
+// LDS access reads both; the workspace tier reads two arrays.
 template <typename IDX, typename SLOT>
 struct LayerTab {
-  const float* hx;
-  const float* hy;
+  static constexpr uint32_t XS = sizeof(SLOT) == 8 ? 2u : 1u;
+  const float* hx;        // x at position p: hx[XS * p]
+  const float* hy;        // y at position p: hy[XS * p] (hx + 1 when interleaved)
   const IDX* kr;          // local index of the hit at each position
   uint8_t* used;
   SLOT* best;             // round winner at the hit (see Cands)
   const IDX* bstart;      // [kNB + 1] first position of every bucket
+  __device__ __forceinline__ float2 xy(uint32_t p) const {
+    if constexpr (XS == 2) return reinterpret_cast<const float2*>(hx)[p];
+    else return make_float2(hx[p], hy[p]);
+  }
 };
 
 template <typename SLOT, typename K>
 struct TrackTab {
   K* slot;          // output slot, counted from the event's first track slot
   K* key0;          // first hit: plane << KSH | local index (orders like its key)
-  float* xa;        // last hit
-  float* ya;
-  float* tx;        // slope through the last two hits
-  float* ty;
+  float4* st;       // last hit (x, y) and slope through the last two hits (z: tx, w: ty),
+                    // one 16-byte access
   uint8_t* la;      // plane of the last hit
   uint8_t* n;       // hits so far
   uint8_t* skip;    // planes missed in a row
@@ -116,7 +121,7 @@ template <typename IDX, bool RING>
 struct FindMem {
   using SLOT = typename CandSlot<RING>::T;
   static constexpr uint32_t KSH = RING ? kPosBits : 22;  // key0 = plane << KSH | local index
-  float* hx;
+  float* hx;         // LDS tiers: x and y interleaved (hy = hx + 1)
   float* hy;
   IDX* kr;
   uint8_t* used;
@@ -142,7 +147,7 @@ struct FindMem {
   __device__ __forceinline__ LayerTab<IDX, SLOT> layer(const EventIO& io, int l) const {
     if constexpr (RING) {
       const uint32_t r = (uint32_t)l % 3u, o = r * capL;
-      return LayerTab<IDX, SLOT>{hx + o, hy + o, kr + o, used + o, best + o, bstart + r * (kNB + 1)};
+      return LayerTab<IDX, SLOT>{hx + 2 * o, hy + 2 * o, kr + o, used + o, best + o, bstart + r * (kNB + 1)};
     } else {
       const uint32_t o = io.lstart[l];
       return LayerTab<IDX, SLOT>{io.X + o, io.Y + o, io.order + o, used + o, best + o,
@@ -227,9 +232,13 @@ struct FindScal {
 // A barrier must separate count from starts and starts from place; the
 // caller's next barrier publishes the slot.  The used flags and round
 // winners of a plane are cleared at the start of its own step.
+// Hits per lane staged by the LDS tiers (their plane capacity is at most
+// kPrefetch * NT; unused register slots would only raise register pressure).
+template <int NT> constexpr int kPrefetch = NT >= 1024 ? 1 : (NT >= 256 ? 2 : 3);
+
 template <int NT, typename IDX, bool RING>
 struct PlanePrefetch {
-  static constexpr int PF = RING ? 4 : 1;              // hits per lane (capL <= 4 NT)
+  static constexpr int PF = RING ? kPrefetch<NT> : 1;  // hits per lane
   float x[PF], y[PF];
   uint32_t br[PF];  // bucket | rank << 16
   uint32_t n = 0;
@@ -287,16 +296,14 @@ struct PlanePrefetch {
   __device__ __forceinline__ void place(const EventIO& io, int l, const MEM& M) {
     if constexpr (RING) {
       const auto t = M.layer(io, l);
-      float* hx = const_cast<float*>(t.hx);
-      float* hy = const_cast<float*>(t.hy);
+      float2* hxy = reinterpret_cast<float2*>(const_cast<float*>(t.hx));
       IDX* kr = const_cast<IDX*>(t.kr);
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
         if (i < n) {
           const uint32_t p = (uint32_t)t.bstart[br[k] & 0xFFFFu] + (br[k] >> 16);
-          hx[p] = x[k];
-          hy[p] = y[k];
+          hxy[p] = make_float2(x[k], y[k]);
           kr[p] = (IDX)i;
         }
       }
@@ -313,8 +320,9 @@ __device__ __forceinline__ void scan_range(const LT& t, uint32_t p, uint32_t e, 
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) {
       const uint32_t q = p + j < e ? p + j : e - 1;
-      x[j] = t.hx[q];
-      y[j] = t.hy[q];
+      const float2 v = t.xy(q);
+      x[j] = v.x;
+      y[j] = v.y;
     }
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j)
@@ -404,8 +412,9 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
     // extrapolation of track t to plane l
     auto extrap = [&](uint32_t t, float& xp, float& yp) {
       const float d = zl - zt[A.la[t]];
-      xp = A.xa[t] + A.tx[t] * d;
-      yp = A.ya[t] + A.ty[t] * d;
+      const float4 v = A.st[t];
+      xp = v.x + v.z * d;
+      yp = v.y + v.w * d;
     };
     auto add_ext = [&](uint32_t t, uint32_t key0, uint32_t h, float s) {
       uint32_t k = atomicAdd(&sc.ncf, 1u);
@@ -474,8 +483,9 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
               for (uint32_t q = 0; q < 4; ++q) {
                 const uint32_t k = (g + q < stop ? g + q : stop - 1) - wb;
                 ph[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
-                xh[q] = T0.hx[ph[q]];
-                yh[q] = T0.hy[ph[q]];
+                const float2 v = T0.xy(ph[q]);
+                xh[q] = v.x;
+                yh[q] = v.y;
               }
   #pragma unroll
               for (uint32_t q = 0; q < 4; ++q) {
@@ -572,12 +582,11 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         if (h != kNone) {
           const uint32_t nn = A.n[t];
           io.hit_idx[26ull * (io.slot_base + A.slot[t]) + nn] = base0 + (uint32_t)T0.kr[h];
-          const float xh = T0.hx[h], yh = T0.hy[h];
+          const float2 vh = T0.xy(h);
+          const float xh = vh.x, yh = vh.y;
           const float dz = zl - zt[A.la[t]];
-          A.tx[t] = (xh - A.xa[t]) / dz;
-          A.ty[t] = (yh - A.ya[t]) / dz;
-          A.xa[t] = xh;
-          A.ya[t] = yh;
+          const float4 v = A.st[t];
+          A.st[t] = make_float4(xh, yh, (xh - v.x) / dz, (yh - v.y) / dz);
           A.la[t] = (uint8_t)l;
           A.n[t] = (uint8_t)(nn + 1);
           A.skip[t] = 0;
@@ -610,8 +619,9 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       const float d12 = z2 - z1;
       // third hit of a doublet (h0, h1): unused, within sqrt(s_seed) of the line
       auto triplets = [&](uint32_t i0, uint32_t i1, float tx, float ty) {
-        const float xp = T1.hx[i1] + tx * d12;
-        const float yp = T1.hy[i1] + ty * d12;
+        const float2 v1 = T1.xy(i1);
+        const float xp = v1.x + tx * d12;
+        const float yp = v1.y + ty * d12;
         Ranges r2 = window(pangle(xp, yp), point_window(xp, yp, P.rho_seed), kNB);
         scan_window(T0, r2, [&](uint32_t i2, float x2, float y2) {
           const float dx = x2 - xp, dy = y2 - yp;
@@ -671,7 +681,8 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           const uint32_t i1 = b0 + tid;
           uint32_t cnt = 0;
           if (i1 < n1 && !T1.used[i1]) {
-            const Ranges r = window(pangle(T1.hx[i1], T1.hy[i1]), P.win_doublet, kNB);
+            const float2 v1 = T1.xy(i1);
+            const Ranges r = window(pangle(v1.x, v1.y), P.win_doublet, kNB);
             const uint32_t s0 = T2.bstart[r.b0], l0 = T2.bstart[r.b1 + 1] - s0;
             uint32_t s1 = 0, l1 = 0;
             if (r.b2 <= r.b3) { s1 = T2.bstart[r.b2]; l1 = T2.bstart[r.b3 + 1] - s1; }
@@ -701,7 +712,8 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
             const uint32_t wb = M.wp[i1], we = M.wp[i1 + 1];
             if (we <= j) continue;
             const uint32_t w0 = M.w0[i1], w1 = M.w1[i1], l0 = w0 >> 16;
-            const float x1 = T1.hx[i1], y1 = T1.hy[i1];
+            const float2 v1 = T1.xy(i1);
+            const float x1 = v1.x, y1 = v1.y;
             const uint32_t stop = we < jend ? we : jend;
             for (uint32_t g = j; g < stop; g += 4) {
               uint32_t pj[4];
@@ -712,8 +724,9 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
                 const uint32_t jj = g + q < stop ? g + q : stop - 1;
                 const uint32_t k = jj - wb;
                 pj[q] = k < l0 ? (w0 & 0xFFFFu) + k : (w1 & 0xFFFFu) + (k - l0);
-                x0[q] = T2.hx[pj[q]];
-                y0[q] = T2.hy[pj[q]];
+                const float2 v0 = T2.xy(pj[q]);
+                x0[q] = v0.x;
+                y0[q] = v0.y;
                 u0[q] = T2.used[pj[q]];
               }
 #pragma unroll
@@ -734,15 +747,17 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         for (uint32_t d = tid; d < nd; d += NT) {
           const Dbl r = M.dbl[d];
           const uint32_t i0 = r & 0xFFFFu, i1 = r >> 16;
-          const float tx = (T1.hx[i1] - T2.hx[i0]) / dz01;
-          const float ty = (T1.hy[i1] - T2.hy[i0]) / dz01;
+          const float2 v1 = T1.xy(i1), v0 = T2.xy(i0);
+          const float tx = (v1.x - v0.x) / dz01;
+          const float ty = (v1.y - v0.y) / dz01;
           triplets(i0, i1, tx, ty);
         }
       } else {
         for (uint32_t i1 = tid; i1 < n1; i1 += NT) {
           if (T1.used[i1]) continue;
-          const Ranges r0 = window(pangle(T1.hx[i1], T1.hy[i1]), P.win_doublet, kNB);
-          const float x1 = T1.hx[i1], y1 = T1.hy[i1];
+          const float2 v1 = T1.xy(i1);
+          const Ranges r0 = window(pangle(v1.x, v1.y), P.win_doublet, kNB);
+          const float x1 = v1.x, y1 = v1.y;
           scan_window(T2, r0, [&](uint32_t i0, float x0, float y0) {
             if (T2.used[i0]) return;
             float tx, ty;
@@ -875,26 +890,24 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
       hi[2] = base0 + (uint32_t)T0.kr[cc];
       const uint32_t pos = n_keep + rank;
       if (pos < M.capT) {
-        const float x1 = T1.hx[cb], y1 = T1.hy[cb], x2 = T0.hx[cc], y2 = T0.hy[cc];
+        const float2 v1 = T1.xy(cb), v2 = T0.xy(cc);
+        const float x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
         const float dz = zl - zt[l + 1];
         A.slot[pos] = (IDX)(created + rank);
         A.key0[pos] = (IDX)(((uint32_t)(l + 2) << M.KSH) | i0);
-        A.xa[pos] = x2;
-        A.ya[pos] = y2;
-        A.tx[pos] = (x2 - x1) / dz;
-        A.ty[pos] = (y2 - y1) / dz;
+        A.st[pos] = make_float4(x2, y2, (x2 - x1) / dz, (y2 - y1) / dz);
         A.la[pos] = (uint8_t)l;
         A.n[pos] = 3;
         A.skip[pos] = 0;
       }
     };
-    struct Keep { uint32_t slot, key0; float xa, ya, tx, ty; uint8_t la, n, skip; };
+    struct Keep { uint32_t slot, key0; float4 st; uint8_t la, n, skip; };
     auto read_keep = [&](uint32_t t) {
-      return Keep{A.slot[t], A.key0[t], A.xa[t], A.ya[t], A.tx[t], A.ty[t], A.la[t], A.n[t], A.skip[t]};
+      return Keep{A.slot[t], A.key0[t], A.st[t], A.la[t], A.n[t], A.skip[t]};
     };
     auto write_keep = [&](uint32_t pos, const Keep& f) {
-      A.slot[pos] = (IDX)f.slot; A.key0[pos] = (IDX)f.key0; A.xa[pos] = f.xa; A.ya[pos] = f.ya;
-      A.tx[pos] = f.tx; A.ty[pos] = f.ty; A.la[pos] = f.la; A.n[pos] = f.n; A.skip[pos] = f.skip;
+      A.slot[pos] = (IDX)f.slot; A.key0[pos] = (IDX)f.key0; A.st[pos] = f.st;
+      A.la[pos] = f.la; A.n[pos] = f.n; A.skip[pos] = f.skip;
     };
     uint32_t n_keep;
     if (n_act <= NT && (!seeds || n2 <= NT)) {
@@ -1016,13 +1029,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
                                                  const uint32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ list_count,
                                                  uint32_t* __restrict__ steal) {
-  __shared__ float s_hx[3 * CAPL], s_hy[3 * CAPL];
+  __shared__ float2 s_hxy[3 * CAPL];  // x, y of every ring position
   __shared__ uint16_t s_kr[3 * CAPL];
   __shared__ uint8_t s_used[3 * CAPL];
   __shared__ uint64_t s_best[3 * CAPL];
   __shared__ uint16_t s_bstart[3 * (kNB + 1)];
   __shared__ uint16_t t_slot[CAPT], t_key0[CAPT];
-  __shared__ float t_xa[CAPT], t_ya[CAPT], t_tx[CAPT], t_ty[CAPT];
+  __shared__ float4 t_st[CAPT];
   __shared__ uint8_t t_la[CAPT], t_n[CAPT], t_skip[CAPT];
   // candidates (priorities, positions) share their space with the seed doublet
   // windows: the windows are dead before the first seed candidate is written,
@@ -1045,14 +1058,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
   M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
-  M.hx = s_hx; M.hy = s_hy; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
+  M.hx = reinterpret_cast<float*>(s_hxy); M.hy = M.hx + 1; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
   M.cnt = s_cnt;
-  M.T = TrackTab<uint64_t, uint16_t>{t_slot, t_key0, t_xa, t_ya, t_tx, t_ty, t_la, t_n, t_skip, t_tbest,
+  M.T = TrackTab<uint64_t, uint16_t>{t_slot, t_key0, t_st, t_la, t_n, t_skip, t_tbest,
                                      t_tmatch};
   M.cand = nullptr;
   M.cprio = s_cw;
   M.cpos = cw + 2 * CAPC;
   M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
+  static_assert(CAPL <= (uint32_t)(kPrefetch<NT> * NT), "a plane's hits fit the lanes' staging registers");
   // work items: events 0..n-1 or list[0..count); round robin over the grid, or
   // stolen from the `steal` counter (persistent workgroups) when it is given
   const uint32_t count = list_count ? *list_count : n_events;
@@ -1071,7 +1085,7 @@ constexpr uint32_t kGBlocks = 128;
 struct GlobalTabs {
   uint32_t* best; uint8_t* used;                                      // [n_pixels]
   uint32_t* slot; uint32_t* key0; uint32_t* tbest; uint32_t* tmatch;  // [n_pixels / 3 + 1]
-  float* xa; float* ya; float* tx; float* ty;
+  float4* st;
   uint8_t* la; uint8_t* n; uint8_t* skip;
   Cand* cand;  // per block: VELO_MAX_CANDIDATES
 };
@@ -1101,7 +1115,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.used = g.used + b;
     M.best = g.best + b;
     const uint64_t tb = b / 3;
-    M.T = TrackTab<uint32_t, uint32_t>{g.slot + tb, g.key0 + tb, g.xa + tb, g.ya + tb, g.tx + tb, g.ty + tb,
+    M.T = TrackTab<uint32_t, uint32_t>{g.slot + tb, g.key0 + tb, g.st + tb,
                    g.la + tb, g.n + tb, g.skip + tb, g.tbest + tb, g.tmatch + tb};
     M.cand = g.cand + (size_t)blockIdx.x * VELO_MAX_CANDIDATES;
     M.cprio = nullptr;
@@ -1172,10 +1186,7 @@ static size_t find_ws_layout(char* w, uint64_t n_pixels, uint32_t n_events, Find
   f.g.key0 = (uint32_t*)take(4 * nt);
   f.g.tbest = (uint32_t*)take(4 * nt);
   f.g.tmatch = (uint32_t*)take(4 * nt);
-  f.g.xa = (float*)take(4 * nt);
-  f.g.ya = (float*)take(4 * nt);
-  f.g.tx = (float*)take(4 * nt);
-  f.g.ty = (float*)take(4 * nt);
+  f.g.st = (float4*)take(16 * nt);
   f.g.la = (uint8_t*)take(nt);
   f.g.n = (uint8_t*)take(nt);
   f.g.skip = (uint8_t*)take(nt);
