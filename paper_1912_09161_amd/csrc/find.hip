@@ -137,6 +137,7 @@ struct FindMem {
   uint32_t* w0;
   uint32_t* w1;
   uint32_t* wp;   // [capL + 1]
+  uint32_t* own;  // [NT] middle hit holding a lane's first pair (one-pass prefix)
   // forward search (LDS tiers): the same for every active track on the next plane
   uint32_t* tw0;
   uint32_t* tw1;
@@ -235,6 +236,10 @@ struct FindScal {
 // Hits per lane staged by the LDS tiers (their plane capacity is at most
 // kPrefetch * NT; unused register slots would only raise register pressure).
 template <int NT> constexpr int kPrefetch = NT >= 1024 ? 1 : (NT >= 256 ? 2 : 3);
+// Candidates per lane in the LDS tiers' conflict rounds (their candidate
+// capacity is at most kCandPerLane * NT): each lane keeps its candidates'
+// positions and priorities in registers for all rounds.
+template <int NT> constexpr int kCandPerLane = NT >= 256 ? 2 : 3;
 
 template <int NT, typename IDX, bool RING>
 struct PlanePrefetch {
@@ -393,8 +398,36 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
   using SLOT = typename CandSlot<RING>::T;
   constexpr SLOT kFree = CandSlot<RING>::kFree;
   // a resource proposes / holds candidate k
-  auto holds = [&](SLOT* slot, uint32_t k) {
-    if constexpr (RING) return __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == M.cprio[k];
+  // The candidates of the conflict rounds, visited by each lane: in the LDS
+  // tiers the lane's own (k = tid + j NT) with their positions and priorities
+  // loaded once into registers (cpos_r, cprio_r); in the workspace tier every
+  // NT-th candidate, read from the table.
+  constexpr int KPL = RING ? kCandPerLane<NT> : 1;
+  uint32_t cpos_r[KPL];
+  uint64_t cprio_r[KPL];
+  auto load_cands = [&](uint32_t nc) {
+    if constexpr (RING) {
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        const uint32_t k = tid + (uint32_t)j * NT;
+        if (k < nc) { cpos_r[j] = M.cpos[k]; cprio_r[j] = M.cprio[k]; }
+      }
+    }
+  };
+  auto for_cands = [&](uint32_t nc, auto f) {
+    if constexpr (RING) {
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        const uint32_t k = tid + (uint32_t)j * NT;
+        if (k < nc) f(k, j);
+      }
+    } else {
+      for (uint32_t k = tid; k < nc; k += NT) f(k, 0);
+    }
+  };
+  // a resource holds candidate k (the lane's j-th)
+  auto holds = [&](SLOT* slot, uint32_t k, int j) {
+    if constexpr (RING) return __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cprio_r[j];
     else return lda(slot) == k;
   };
   for (int l = kLayers - 1; l >= 0; --l) {
@@ -530,48 +563,48 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
             if (ci.s != cj.s) return ci.s < cj.s;
             return T0.kr[ci.b] < T0.kr[cj.b];
           };
-          // (track, hit) of candidate k
-          auto th = [&](uint32_t k, uint32_t& t, uint32_t& h) {
-            if constexpr (RING) { const uint32_t v = M.cpos[k]; t = v & kPosMask; h = v >> kPosBits; }
+          // (track, hit) of candidate k, the lane's j-th
+          auto th = [&](uint32_t k, int j, uint32_t& t, uint32_t& h) {
+            if constexpr (RING) { const uint32_t v = cpos_r[j]; t = v & kPosMask; h = v >> kPosBits; }
             else { const Cand c = M.cand[k]; t = c.a; h = c.b; }
           };
           auto live = [&](uint32_t t, uint32_t h) { return A.tmatch[t] == kNone && !T0.used[h]; };
+          load_cands(nc);
           greedy_rounds<RING>(
               nc, sc,
               [&] {
-                for (uint32_t k = tid; k < nc; k += NT) {
+                for_cands(nc, [&](uint32_t k, int j) {
                   uint32_t t, h;
-                  th(k, t, h);
-                  if (!live(t, h)) continue;
+                  th(k, j, t, h);
+                  if (!live(t, h)) return;
                   if constexpr (RING) {
-                    const uint64_t pr = M.cprio[k];
-                    atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)pr);
-                    atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)pr);
+                    atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)cprio_r[j]);
+                    atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)cprio_r[j]);
                   } else {
                     cas_min(T0.best + h, k, less_hit);
                     cas_min(A.tbest + t, k, less_trk);
                   }
-                }
+                });
               },
               [&] {
-                for (uint32_t k = tid; k < nc; k += NT) {
+                for_cands(nc, [&](uint32_t k, int j) {
                   uint32_t t, h;
-                  th(k, t, h);
-                  if (live(t, h) && holds(T0.best + h, k) && holds(A.tbest + t, k)) {
+                  th(k, j, t, h);
+                  if (live(t, h) && holds(T0.best + h, k, j) && holds(A.tbest + t, k, j)) {
                     A.tmatch[t] = h;
                     T0.used[h] = 1;
                   }
-                }
+                });
               },
               [&] {
                 bool any = false;
-                for (uint32_t k = tid; k < nc; k += NT) {
+                for_cands(nc, [&](uint32_t k, int j) {
                   uint32_t t, h;
-                  th(k, t, h);
+                  th(k, j, t, h);
                   T0.best[h] = kFree;
                   A.tbest[t] = kFree;
                   if (live(t, h)) any = true;
-                }
+                });
                 return any;
               });
         }
@@ -693,6 +726,12 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           uint32_t tot;
           const uint32_t ex = scan(cnt, &tot);
           if (i1 < n1) M.wp[i1] = carry + ex;
+          if (n1 <= NT && cnt > 0) {
+            // one pass: the middle hit whose pairs contain a lane's first pair
+            // (below) is known here, so that lane need not search for it
+            const uint32_t per = (tot + NT - 1) / NT;
+            for (uint32_t L = (ex + per - 1) / per; L * per < ex + cnt; ++L) M.own[L] = i1;
+          }
           carry += tot;
         }
         if (tid == 0) M.wp[n1] = carry;
@@ -704,9 +743,13 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         const uint32_t jend = j + per < total ? j + per : total;
         if (j < jend) {
           uint32_t lo = 0, hi = n1 - 1;
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (M.wp[mid] <= j) lo = mid; else hi = mid - 1;
+          if (n1 <= NT) {
+            lo = M.own[tid];
+          } else {
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi + 1) >> 1;
+              if (M.wp[mid] <= j) lo = mid; else hi = mid - 1;
+            }
           }
           for (uint32_t i1 = lo; j < jend; ++i1) {
             const uint32_t wb = M.wp[i1], we = M.wp[i1 + 1];
@@ -784,10 +827,10 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           if (ci.a != cj.a) return T2.kr[ci.a] < T2.kr[cj.a];
           return T0.kr[ci.c] < T0.kr[cj.c];
         };
-        // hits (h0, h1, h2) of candidate k
-        auto hits3 = [&](uint32_t k, uint32_t& i0, uint32_t& i1, uint32_t& i2) {
+        // hits (h0, h1, h2) of candidate k, the lane's j-th
+        auto hits3 = [&](uint32_t k, int j, uint32_t& i0, uint32_t& i1, uint32_t& i2) {
           if constexpr (RING) {
-            const uint32_t v = M.cpos[k];
+            const uint32_t v = cpos_r[j];
             i0 = v & kPosMask; i1 = (v >> kPosBits) & kPosMask; i2 = (v >> (2 * kPosBits)) & kPosMask;
           } else {
             const Cand c = M.cand[k]; i0 = c.a; i1 = c.b; i2 = c.c;
@@ -796,15 +839,16 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         auto alive = [&](uint32_t i0, uint32_t i1, uint32_t i2) {
           return !T2.used[i0] && !T1.used[i1] && !T0.used[i2];
         };
+        load_cands(nc);
         greedy_rounds<RING>(
             nc, sc,
             [&] {
-              for (uint32_t k = tid; k < nc; k += NT) {
+              for_cands(nc, [&](uint32_t k, int j) {
                 uint32_t i0, i1, i2;
-                hits3(k, i0, i1, i2);
-                if (!alive(i0, i1, i2)) continue;
+                hits3(k, j, i0, i1, i2);
+                if (!alive(i0, i1, i2)) return;
                 if constexpr (RING) {
-                  const unsigned long long pr = M.cprio[k];
+                  const unsigned long long pr = cprio_r[j];
                   atomicMin((unsigned long long*)(T2.best + i0), pr);
                   atomicMin((unsigned long long*)(T1.best + i1), pr);
                   atomicMin((unsigned long long*)(T0.best + i2), pr);
@@ -813,44 +857,44 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
                   cas_min(T1.best + i1, k, less_seed);
                   cas_min(T0.best + i2, k, less_seed);
                 }
-              }
+              });
             },
             [&] {
-              for (uint32_t k = tid; k < nc; k += NT) {
+              for_cands(nc, [&](uint32_t k, int j) {
                 uint32_t i0, i1, i2;
-                hits3(k, i0, i1, i2);
-                if (alive(i0, i1, i2) && holds(T2.best + i0, k) && holds(T1.best + i1, k) &&
-                    holds(T0.best + i2, k)) {
+                hits3(k, j, i0, i1, i2);
+                if (alive(i0, i1, i2) && holds(T2.best + i0, k, j) && holds(T1.best + i1, k, j) &&
+                    holds(T0.best + i2, k, j)) {
                   T2.used[i0] = 1;
                   T1.used[i1] = 1;
                   T0.used[i2] = 1;
-                  if constexpr (RING) M.cpos[k] |= kAccepted;
+                  if constexpr (RING) cpos_r[j] |= kAccepted;
                   else M.cand[k].s = -1.0f;  // accepted (every real s is >= 0)
                 }
-              }
+              });
             },
             [&] {
               bool any = false;
-              for (uint32_t k = tid; k < nc; k += NT) {
+              for_cands(nc, [&](uint32_t k, int j) {
                 uint32_t i0, i1, i2;
-                hits3(k, i0, i1, i2);
+                hits3(k, j, i0, i1, i2);
                 T2.best[i0] = kFree;
                 T1.best[i1] = kFree;
                 T0.best[i2] = kFree;
                 if (alive(i0, i1, i2)) any = true;
-              }
+              });
               return any;
             });
         // accepted seed of each h0, stored by the local index of h0 (the slots
         // are clear; nothing reads plane l+2 by position any more)
-        for (uint32_t k = tid; k < nc; k += NT) {
+        for_cands(nc, [&](uint32_t k, int j) {
           uint32_t i0, i1, i2;
-          hits3(k, i0, i1, i2);
+          hits3(k, j, i0, i1, i2);
           bool acc;
-          if constexpr (RING) acc = (M.cpos[k] & kAccepted) != 0;
+          if constexpr (RING) acc = (cpos_r[j] & kAccepted) != 0;
           else acc = M.cand[k].s < 0.0f;
           if (acc) T2.best[T2.kr[i0]] = (SLOT)k;
-        }
+        });
         wg_barrier<RING>();
       }
     }
@@ -1040,7 +1084,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   // candidates (priorities, positions) share their space with the seed doublet
   // windows: the windows are dead before the first seed candidate is written,
   // and extension candidates are dead before the windows are built
-  constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u);
+  constexpr uint32_t kCandBytes = 12u * CAPC, kWinBytes = 4u * (3u * CAPL + 1u + NT);
   __shared__ uint64_t s_cw[((kCandBytes > kWinBytes ? kCandBytes : kWinBytes) + 7u) / 8u];
   // the matches and round winners of the extension step share their space with
   // the seed doublets: the doublets are written after the barrier that ends
@@ -1057,7 +1101,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   FindMem<uint16_t, true> M;
   M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
-  M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
+  M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.own = cw + 3 * CAPL + 1; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
   M.hx = reinterpret_cast<float*>(s_hxy); M.hy = M.hx + 1; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
   M.cnt = s_cnt;
   M.T = TrackTab<uint64_t, uint16_t>{t_slot, t_key0, t_st, t_la, t_n, t_skip, t_tbest,
@@ -1067,6 +1111,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   M.cpos = cw + 2 * CAPC;
   M.capL = CAPL; M.capT = CAPT; M.capC = CAPC;
   static_assert(CAPL <= (uint32_t)(kPrefetch<NT> * NT), "a plane's hits fit the lanes' staging registers");
+  static_assert(CAPC <= (uint32_t)(kCandPerLane<NT> * NT), "the candidates fit the lanes' registers");
   // work items: events 0..n-1 or list[0..count); round robin over the grid, or
   // stolen from the `steal` counter (persistent workgroups) when it is given
   const uint32_t count = list_count ? *list_count : n_events;
@@ -1123,7 +1168,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.capL = ne;
     M.capT = (uint32_t)((b + ne) / 3 - b / 3);
     M.capC = VELO_MAX_CANDIDATES;
-    M.w0 = M.w1 = M.wp = nullptr;
+    M.w0 = M.w1 = M.wp = M.own = nullptr;
     M.tw0 = M.tw1 = M.twp = nullptr;
     M.dbl = nullptr;
     M.capD = 0;
