@@ -142,6 +142,7 @@ struct FindMem {
   uint32_t* tw0;
   uint32_t* tw1;
   uint32_t* twp;  // [capT + 1]
+  uint32_t* twown;  // [NT] track holding a lane's first pair (one-pass prefix)
   Dbl* dbl;       // [capD]
   uint32_t* cnt;  // [kNB / 2] bucket counters of the plane being staged, 16 bits each (LDS tiers)
   uint32_t capL, capT, capC, capD;
@@ -348,13 +349,16 @@ __device__ __forceinline__ void scan_window(const LT& t, Ranges r, F f) {
 // winners' slots are cleared in the same phase that looks for live
 // candidates, and the flag alternates between two words so it is cleared a
 // round ahead.  Invariant: every best/tbest slot is kNone before and after,
-// and both flags are 0.
+// and both flags are 0.  Every candidate is live in the first round, so
+// propose(true) skips the test; a candidate that holds all of its resources
+// is live (a dead one proposed nothing this round, and priorities are
+// unique), so acceptance needs no test either.
 template <bool RING, typename PROPOSE, typename ACCEPT, typename CLEAR>
 __device__ __forceinline__ void greedy_rounds(uint32_t nc, FindScal& sc, PROPOSE propose,
                                               ACCEPT accept, CLEAR clear_and_live) {
   const uint32_t tid = threadIdx.x;
   for (uint32_t round = 0; round <= nc; ++round) {
-    propose();
+    propose(round == 0);
     wg_barrier<RING>();
     accept();
     wg_barrier<RING>();
@@ -487,6 +491,11 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           uint32_t tot;
           const uint32_t ex = scan(cnt, &tot);
           if (t < n_act) M.twp[t] = carry + ex;
+          if (n_act <= NT && cnt > 0) {
+            // one pass: the track whose pairs contain a lane's first pair
+            const uint32_t per = (tot + NT - 1) / NT;
+            for (uint32_t L = (ex + per - 1) / per; L * per < ex + cnt; ++L) M.twown[L] = t;
+          }
           carry += tot;
         }
         if (tid == 0) M.twp[n_act] = carry;
@@ -498,9 +507,13 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         const uint32_t jend = j + per < total ? j + per : total;
         if (j < jend) {
           uint32_t lo = 0, hi = n_act - 1;
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (M.twp[mid] <= j) lo = mid; else hi = mid - 1;
+          if (n_act <= NT) {
+            lo = M.twown[tid];
+          } else {
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi + 1) >> 1;
+              if (M.twp[mid] <= j) lo = mid; else hi = mid - 1;
+            }
           }
           for (uint32_t t = lo; j < jend; ++t) {
             const uint32_t wb = M.twp[t], we = M.twp[t + 1];
@@ -572,11 +585,11 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
           load_cands(nc);
           greedy_rounds<RING>(
               nc, sc,
-              [&] {
+              [&](bool first) {
                 for_cands(nc, [&](uint32_t k, int j) {
                   uint32_t t, h;
                   th(k, j, t, h);
-                  if (!live(t, h)) return;
+                  if (!first && !live(t, h)) return;
                   if constexpr (RING) {
                     atomicMin((unsigned long long*)(T0.best + h), (unsigned long long)cprio_r[j]);
                     atomicMin((unsigned long long*)(A.tbest + t), (unsigned long long)cprio_r[j]);
@@ -590,7 +603,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
                 for_cands(nc, [&](uint32_t k, int j) {
                   uint32_t t, h;
                   th(k, j, t, h);
-                  if (live(t, h) && holds(T0.best + h, k, j) && holds(A.tbest + t, k, j)) {
+                  if (holds(T0.best + h, k, j) && holds(A.tbest + t, k, j)) {
                     A.tmatch[t] = h;
                     T0.used[h] = 1;
                   }
@@ -842,11 +855,11 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
         load_cands(nc);
         greedy_rounds<RING>(
             nc, sc,
-            [&] {
+            [&](bool first) {
               for_cands(nc, [&](uint32_t k, int j) {
                 uint32_t i0, i1, i2;
                 hits3(k, j, i0, i1, i2);
-                if (!alive(i0, i1, i2)) return;
+                if (!first && !alive(i0, i1, i2)) return;
                 if constexpr (RING) {
                   const unsigned long long pr = cprio_r[j];
                   atomicMin((unsigned long long*)(T2.best + i0), pr);
@@ -863,7 +876,7 @@ __device__ __forceinline__ uint32_t find_event(const EventIO& io, const FindCons
               for_cands(nc, [&](uint32_t k, int j) {
                 uint32_t i0, i1, i2;
                 hits3(k, j, i0, i1, i2);
-                if (alive(i0, i1, i2) && holds(T2.best + i0, k, j) && holds(T1.best + i1, k, j) &&
+                if (holds(T2.best + i0, k, j) && holds(T1.best + i1, k, j) &&
                     holds(T0.best + i2, k, j)) {
                   T2.used[i0] = 1;
                   T1.used[i1] = 1;
@@ -1095,11 +1108,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
   __shared__ uint64_t s_td[kTdBytes / 8];
   uint32_t* t_tmatch = reinterpret_cast<uint32_t*>(s_td);
   uint64_t* t_tbest = s_td + CAPT / 2;
-  __shared__ uint32_t s_tw[NT >= 512 ? 3 * CAPT + 1 : 1];  // balanced forward search only
+  __shared__ uint32_t s_tw[NT >= 512 ? 3 * CAPT + 1 + NT : 1];  // balanced forward search only
   __shared__ uint32_t s_cnt[kNB / 2];  // bucket counters of the plane being staged
   __shared__ FindScal sc;
   FindMem<uint16_t, true> M;
-  M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT;
+  M.tw0 = s_tw; M.tw1 = s_tw + CAPT; M.twp = s_tw + 2 * CAPT; M.twown = s_tw + 3 * CAPT + 1;
   uint32_t* cw = reinterpret_cast<uint32_t*>(s_cw);
   M.w0 = cw; M.w1 = cw + CAPL; M.wp = cw + 2 * CAPL; M.own = cw + 3 * CAPL + 1; M.dbl = reinterpret_cast<Dbl*>(s_td); M.capD = CAPD;
   M.hx = reinterpret_cast<float*>(s_hxy); M.hy = M.hx + 1; M.kr = s_kr; M.used = s_used; M.best = s_best; M.bstart = s_bstart;
@@ -1169,7 +1182,7 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
     M.capT = (uint32_t)((b + ne) / 3 - b / 3);
     M.capC = VELO_MAX_CANDIDATES;
     M.w0 = M.w1 = M.wp = M.own = nullptr;
-    M.tw0 = M.tw1 = M.twp = nullptr;
+    M.tw0 = M.tw1 = M.twp = M.twown = nullptr;
     M.dbl = nullptr;
     M.capD = 0;
     M.cnt = nullptr;
