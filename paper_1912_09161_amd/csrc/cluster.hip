@@ -123,6 +123,9 @@ template <int NT, bool PACKED, uint32_t MAXW>
 __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, uint32_t layer,
                                     const SegScratch<PACKED>& S, HitsOut o, uint64_t out_base) {
   constexpr uint32_t WPL = (RowTab<PACKED>::kWords + NT - 1) / NT;  // row words per lane
+  // the lanes' words tile the row table in 16-byte pieces: they are cleared,
+  // read and written as such (the table is 16-byte aligned)
+  constexpr bool VEC = NT * WPL == RowTab<PACKED>::kWords && WPL % 4 == 0;
   const uint32_t tid = threadIdx.x;
   const RowTab<PACKED> rt{S.rows};
   constexpr uint32_t RW = MAXW > 0 ? MAXW : 1;
@@ -134,7 +137,13 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
       wr[k] = i < n ? w[i] : 0u;
     }
   }
-  for (uint32_t i = tid; i < RowTab<PACKED>::kWords; i += NT) S.rows[i] = 0;
+  if constexpr (VEC) {
+#pragma unroll
+    for (uint32_t k = 0; k < WPL; k += 4)
+      *reinterpret_cast<uint4*>(S.rows + tid * WPL + k) = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    for (uint32_t i = tid; i < RowTab<PACKED>::kWords; i += NT) S.rows[i] = 0;
+  }
   if (tid == 0) *S.flag = 0;
   __syncthreads();
   if constexpr (MAXW > 0) {
@@ -148,24 +157,40 @@ __device__ uint32_t cluster_segment(const uint32_t* __restrict__ w, uint32_t n, 
   {  // row starts: exclusive prefix over rows, WPL consecutive words per lane
     const uint32_t w0 = tid * WPL;
     uint32_t c[WPL], sum = 0;
+    if constexpr (VEC) {
 #pragma unroll
-    for (uint32_t k = 0; k < WPL; ++k) {
-      c[k] = w0 + k < RowTab<PACKED>::kWords ? ld(S.rows + w0 + k) : 0u;
-      sum += PACKED ? (c[k] & 0xFFFFu) + (c[k] >> 16) : c[k];
+      for (uint32_t k = 0; k < WPL; k += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(S.rows + w0 + k);
+        c[k] = v.x; c[k + 1] = v.y; c[k + 2] = v.z; c[k + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < WPL; ++k) c[k] = w0 + k < RowTab<PACKED>::kWords ? ld(S.rows + w0 + k) : 0u;
     }
+#pragma unroll
+    for (uint32_t k = 0; k < WPL; ++k) sum += PACKED ? (c[k] & 0xFFFFu) + (c[k] >> 16) : c[k];
     uint32_t tot;
     uint32_t run = block_scan<NT>(sum, S.tmp, &tot);
+    uint32_t o[WPL];
 #pragma unroll
     for (uint32_t k = 0; k < WPL; ++k) {
-      if (w0 + k >= RowTab<PACKED>::kWords) continue;
       if constexpr (PACKED) {
         const uint32_t lo = run, hi = run + (c[k] & 0xFFFFu);
-        S.rows[w0 + k] = lo | (hi << 16);
+        o[k] = lo | (hi << 16);
         run = hi + (c[k] >> 16);
       } else {
-        S.rows[w0 + k] = run;
+        o[k] = run;
         run += c[k];
       }
+    }
+    if constexpr (VEC) {
+#pragma unroll
+      for (uint32_t k = 0; k < WPL; k += 4)
+        *reinterpret_cast<uint4*>(S.rows + w0 + k) = make_uint4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < WPL; ++k)
+        if (w0 + k < RowTab<PACKED>::kWords) S.rows[w0 + k] = o[k];
     }
   }
   __syncthreads();
@@ -403,7 +428,7 @@ struct SmallArgs {
 
 struct SmallLds {
   // the row table and the cluster sums are never live together
-  union {
+  union alignas(16) {
     uint32_t rows[kPix / 2];
     uint64_t scr[kSmallCap];
   } rs;
