@@ -335,14 +335,14 @@ typedef struct velo_context velo_context;
 velo_status velo_context_create(velo_context** ctx, const velo_geometry* geom,
                                 const velo_params* params);
 void velo_context_destroy(velo_context* ctx);
-/* out12 = {how the shapes were chosen (0 not yet, 1 tuned on this context's
+/* out13 = {how the shapes were chosen (0 not yet, 1 tuned on this context's
    first batch, 2 taken from the process-wide tune cache, 3 set by
    velo_context_set_config), clustering grid (0 = one workgroup per segment),
    large-segment grid, track-finding lanes per event, track-finding grid
    (0 = one workgroup per event), fit lanes per event, then the workgroups of
    the three track-finding tiers that take the events the first one hands on
    (middle 512 lanes, large 1024 lanes, workspace tier), routing, fork,
-   event order}.
+   event order, tiny tier}.
    The tuner picks those three as the smallest of {512, 256, 128},
    {64, 32, 32}, {16, 8, 8} within 2 % of the best tuning-stream time: a
    tier's launch keeps its grid's LDS reserved until every workgroup has been
@@ -353,11 +353,15 @@ void velo_context_destroy(velo_context* ctx);
    events runs on a side stream the context owns, beside the first tier, and
    joins the caller's stream before the next tier (inside captured graphs
    too).  Event order 1 (one workgroup per event only): the first tier's
-   workgroups take the events largest first.  The tuner tries order,
-   routing by plane capacity and fork only for batches of 8192 events or
-   more (a smaller batch starts all its events at once, and beside other
-   streams the extra kernels cost more than they save) and takes them only
-   when they beat none of them by 1 %.  tuned_ms5 (may be
+   workgroups take the events largest first.  Tiny tier 1 (one workgroup
+   per event, 256 lanes, no routing): a tier for at most 192 hits per plane,
+   192 active tracks, 256 candidates and 512 doublets, six workgroups per CU,
+   runs every event first and hands the others on to the small tier.  The
+   tuner tries order, routing by plane capacity and fork only for batches
+   of 8192 events or more (a smaller batch starts all its events at once,
+   and beside other streams the extra kernels cost more than they save),
+   the tiny tier for any batch, and takes them only when they beat none of
+   them by 1 %.  tuned_ms5 (may be
    NULL) = tuning-stream times of the chosen clustering, track-finding and fit
    shapes, then the best clustering time with one workgroup per segment and
    the best track-finding time with one workgroup per event (zeros when set
@@ -367,19 +371,20 @@ void velo_context_destroy(velo_context* ctx);
    quarter-octave classes), the classifier flag and the parameters: a new
    context whose first batch falls in a cached class takes the shapes from
    there without timing anything.                                           */
-velo_status velo_context_config(const velo_context* ctx, int32_t* out12, float* tuned_ms5);
+velo_status velo_context_config(const velo_context* ctx, int32_t* out13, float* tuned_ms5);
 /* Fix the launch shapes of a context instead of tuning them (for callers that
    know their workload, and for tests that run every shape):
-   in11 = {clustering grid 0..65536 (0 = one workgroup per segment),
+   in12 = {clustering grid 0..65536 (0 = one workgroup per segment),
    large-segment grid 1..65536, track-finding lanes 128 or 256, track-finding
    grid 0..65536 (0 = one workgroup per event), fit lanes 64, 128 or 256,
    middle-tier workgroups 1..512, large-tier workgroups 1..256,
    workspace-tier workgroups 1..128, routing -1..2^31-1 (non-zero only with
    track-finding grid 0), fork 0 or 1 (1 only with routing), event order 0
-   or 1 (1 only with track-finding grid 0)}.
+   or 1 (1 only with track-finding grid 0), tiny tier 0 or 1 (1 only with
+   track-finding grid 0, 256 lanes and no routing)}.
    Other values return VELO_ERR_ARG and leave the context unchanged.  Drops
    the context's captured graphs; results do not depend on the shapes.      */
-velo_status velo_context_set_config(velo_context* ctx, const int32_t* in11);
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in12);
 size_t velo_batched_workspace_bytes(uint64_t n_pixels, uint32_t n_events);
 velo_status velo_reconstruct_batched(velo_context* ctx, const uint32_t* d_pixels,
                                      const uint64_t* d_offsets, uint32_t n_events, uint64_t n_pixels,

@@ -165,6 +165,7 @@ struct BatchedCfg {
   uint32_t route_hits;   // events routed past the small track-finding tier (0: none; find_grid == 0)
   uint32_t fork;         // routed events' middle tier on the side stream, beside the small tier
   uint32_t find_order;   // find_grid == 0: workgroups take the events largest first
+  uint32_t tiny;         // find_grid == 0, no routing, 256 lanes: the tiny tier ahead of the small one
 };
 
 // The side stream and the two events of a fork (side == null: no fork).
@@ -227,7 +228,8 @@ static hipError_t enqueue_batched(const BatchedCall& c, const BatchedCfg& k, hip
     const bool fork = k.fork && k.route_hits && fk.side;
     const FindCfg fc{k.find_threads, k.find_grid, ow.ev_order, ow.counters + 2,
                      {k.esc_grid[0], k.esc_grid[1], k.esc_grid[2]}, k.find_grid ? 0u : k.route_hits,
-                     fork ? fk.side : nullptr, fk.fork_ev, fk.join_ev, k.find_grid ? 0u : k.find_order};
+                     fork ? fk.side : nullptr, fk.fork_ev, fk.join_ev, k.find_grid ? 0u : k.find_order,
+                     k.find_grid || k.route_hits || k.find_threads != kSThreads ? 0u : k.tiny};
     hipError_t e = launch_find_cfg(&c.hits, c.offsets, c.n_events, c.n_pixels, &c.params, &c.tracks,
                                    c.ws, s, fc);
     if (e != hipSuccess) return e;
@@ -258,7 +260,7 @@ struct velo_context {
   velo_params params{};  // used when a call passes no parameters
   bool tuned = false;
   int source = 0;  // how cfg was chosen: 1 tuned here, 2 tune cache, 3 set by the caller
-  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128, {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks}, 0, 0, 0};
+  velo::BatchedCfg cfg{2048, 512, 256, 1024, 128, {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks}, 0, 0, 0, 0};
   // side stream and events of the forked track-finding tier, made with the
   // context on side_dev (calls on another device run unforked)
   velo::Fork fork{nullptr, nullptr, nullptr};
@@ -407,29 +409,34 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     for (int i = 0; i < 3; ++i)
       if (et[i] <= 1.02f * tbest) pe = i;
     for (int j = 0; j < 3; ++j) best.esc_grid[j] = esc[pe][j];
-    // one workgroup per event, batches that fill the GPU on their own (at
-    // least 8192 events; a smaller batch starts all its events at once, and
-    // beside other streams the extra kernels and launches cost more than they
-    // save): the events largest first (a shorter tail), and routing: events
-    // the small tier would hand on after part of their work (a plane above
-    // its capacity) go straight to the middle
-    // tier, which, with a fork, runs beside the small tier.  Taken only when
-    // they beat the plain order by 1 % on the tuning stream.  The tier grids
-    // are tried again at full size, which the routed events may need.
-    if (best.find_grid == 0 && c.n_events >= 8192) {
-      constexpr int kNR = 5;
-      const uint32_t ro[kNR][3] = {// order, route, fork
-                                   {1, 0, 0}, {0, 0xFFFFFFFFu, 0}, {1, 0xFFFFFFFFu, 0},
-                                   {0, 0xFFFFFFFFu, 1}, {1, 0xFFFFFFFFu, 1}};
-      const bool can_fork = fk.side != nullptr;
+    // One workgroup per event: the tiny tier ahead of the small one (six
+    // workgroups per CU for the events within its capacities; the others are
+    // handed on at once or after part of their work), and, for batches that
+    // fill the GPU on their own (at least 8192 events; a smaller batch
+    // starts all its events at once, and beside other streams the extra
+    // kernels and launches cost more than they save): the events largest
+    // first (a shorter tail), and routing: events with a plane above the small
+    // tier's capacity go straight to the middle tier, which, with a fork, runs
+    // beside the small tier.  Taken only when they beat the plain sequence by
+    // 1 % on the tuning stream.  The tier grids are tried again at full size,
+    // which the routed events may need.
+    if (best.find_grid == 0) {
+      constexpr int kNR = 7;
+      const uint32_t ro[kNR][4] = {// tiny, order, route, fork
+                                   {1, 0, 0, 0}, {1, 1, 0, 0}, {0, 1, 0, 0}, {0, 0, 0xFFFFFFFFu, 0},
+                                   {0, 1, 0xFFFFFFFFu, 0}, {0, 0, 0xFFFFFFFFu, 1}, {0, 1, 0xFFFFFFFFu, 1}};
+      const bool big = c.n_events >= 8192, can_fork = fk.side != nullptr;
       float rbest = tbest;
       BatchedCfg k3 = best, rpick = best;
       for (int i = 0; i < kNR; ++i) {
-        if (ro[i][2] && !can_fork) continue;
+        if (ro[i][0] && best.find_threads != kSThreads) continue;
+        if ((ro[i][1] || ro[i][2]) && !big) continue;
+        if (ro[i][3] && !can_fork) continue;
         for (int g = 0; g < (pe == 0 ? 1 : 2); ++g) {
-          k3.find_order = ro[i][0];
-          k3.route_hits = ro[i][1];
-          k3.fork = ro[i][2];
+          k3.tiny = ro[i][0];
+          k3.find_order = ro[i][1];
+          k3.route_hits = ro[i][2];
+          k3.fork = ro[i][3];
           for (int j = 0; j < 3; ++j) k3.esc_grid[j] = esc[g == 0 ? pe : 0][j];
           if ((e = time_stage(c, k3, fk, 2, s, 3, &t)) != hipSuccess) return e;
           if (t < rbest) { rbest = t; rpick = k3; }

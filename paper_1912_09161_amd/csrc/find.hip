@@ -1082,7 +1082,7 @@ __device__ __forceinline__ bool run_event(const FindArgs& a, const FindConst& P,
 // LDS tiers: one event per workgroup (list == nullptr) or a persistent loop
 // over a list of events.
 template <int NT, uint32_t CAPL, uint32_t CAPT, uint32_t CAPC, uint32_t CAPD>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 5 : (NT >= 512 ? 4 : 1)))) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? (CAPL <= 192 ? 6 : 5) : (NT >= 512 ? 4 : 1)))) void k_find_lds(FindArgs a, FindConst P, uint32_t n_events,
                                                  const uint32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ list_count,
                                                  uint32_t* __restrict__ steal) {
@@ -1198,6 +1198,9 @@ __global__ __launch_bounds__(kGThreads) void k_find_global(FindArgs a, FindConst
 // small LDS tier: one workgroup per event
 constexpr int kSThreads = 256;
 constexpr uint32_t kSCapL = 288, kSCapT = 256, kSCapC = 384, kSCapD = 3 * kSCapT;
+// tiny LDS tier (batched form, optional, ahead of the small tier): 23.5 KB of
+// LDS and at most 80 VGPRs, so six workgroups share a CU instead of five
+constexpr uint32_t kTCapL = 192, kTCapT = 192, kTCapC = 256, kTCapD = 512;
 // middle and large LDS tiers: persistent workgroups over the events the tier
 // below hands on
 constexpr int kMThreads = 512;
@@ -1210,7 +1213,8 @@ static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct FindWs {
   uint32_t* esc_counts;  // [5] list lengths: small -> middle -> large -> workspace tier hand-overs,
-                         // then the routed events and the small tier's events (routing)
+                         // then the routed events (or the tiny tier's hand-overs) and the small
+                         // tier's events (routing)
   uint32_t *esc_count, *esc_list, *esc2_count, *esc2_list, *esc3_count, *esc3_list, *order, *bst;
   uint32_t *route_count, *route_list, *small_count, *small_list;
   float *xs, *ys;
@@ -1297,6 +1301,9 @@ struct FindCfg {
   // small_grid == 0: the small tier (and routing) takes the events in
   // ev_order (largest first) instead of index order
   uint32_t ordered;
+  // small_grid == 0, no routing, 256 lanes: the tiny tier runs every event
+  // first and hands on to the small tier those above its capacities
+  uint32_t tiny;
 };
 
 static uint32_t tier_grid(uint32_t want, uint32_t full) { return want == 0 || want > full ? full : want; }
@@ -1371,6 +1378,16 @@ hipError_t launch_find_cfg(const velo_hits* h, const uint64_t* offsets, uint32_t
   const uint32_t* slist = route ? f.small_list : order;
   const uint32_t* scount = route ? f.small_count : (const uint32_t*)nullptr;
   if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
+  if (cfg.tiny && !route && !ws_mode && cfg.small_threads == kSThreads) {
+    // the tiny tier's hand-overs go through the (otherwise unused) routing list
+    FindArgs a0 = a;
+    a0.esc_count = f.route_count;
+    a0.esc_list = f.route_list;
+    hipLaunchKernelGGL((k_find_lds<kSThreads, kTCapL, kTCapT, kTCapC, kTCapD>), grid, dim3(kSThreads), 0, s, a0,
+                       c, n_events, slist, scount, (uint32_t*)nullptr);
+    slist = f.route_list;
+    scount = f.route_count;
+  }
   if (cfg.small_threads == 128)
     hipLaunchKernelGGL((k_find_lds<128, kSCapL, kSCapT, kSCapC, kSCapD>), grid, dim3(128), 0, s, a, c,
                        n_events, slist, scount, steal);
@@ -1400,7 +1417,7 @@ hipError_t launch_find(const velo_hits* h, const uint64_t* offsets, uint32_t n_e
                        uint64_t n_pixels, const velo_params* p, const velo_tracks* t, void* ws,
                        hipStream_t s) {
   return launch_find_cfg(h, offsets, n_events, n_pixels, p, t, ws, s,
-                         FindCfg{kSThreads, 0, nullptr, nullptr, {0, 0, 0}, 0, nullptr, nullptr, nullptr, 0});
+                         FindCfg{kSThreads, 0, nullptr, nullptr, {0, 0, 0}, 0, nullptr, nullptr, nullptr, 0, 0});
 }
 
 }  // namespace velo

@@ -401,22 +401,24 @@ void velo_context_destroy(velo_context* ctx) {
   delete ctx;
 }
 
-velo_status velo_context_set_config(velo_context* ctx, const int32_t* in11) {
-  if (!ctx || !in11) return VELO_ERR_ARG;
-  const int32_t cg = in11[0], mg = in11[1], ft = in11[2], fg = in11[3], fit = in11[4];
-  const int32_t route = in11[8], fork = in11[9], order = in11[10];
+velo_status velo_context_set_config(velo_context* ctx, const int32_t* in12) {
+  if (!ctx || !in12) return VELO_ERR_ARG;
+  const int32_t cg = in12[0], mg = in12[1], ft = in12[2], fg = in12[3], fit = in12[4];
+  const int32_t route = in12[8], fork = in12[9], order = in12[10], tiny = in12[11];
   if (cg < 0 || cg > 65536 || mg < 1 || mg > 65536 || (ft != 128 && ft != 256) || fg < 0 ||
       fg > 65536 || (fit != 64 && fit != 128 && fit != 256))
     return VELO_ERR_ARG;
   if (route < -1 || (route != 0 && fg != 0) || (fork != 0 && fork != 1) || (fork && !route) ||
-      (order != 0 && order != 1) || (order && fg != 0))
+      (order != 0 && order != 1) || (order && fg != 0) || (tiny != 0 && tiny != 1) ||
+      (tiny && (fg != 0 || route != 0 || ft != 256)))
     return VELO_ERR_ARG;
   const uint32_t full[3] = {velo::kMBlocks, velo::kLBlocks, velo::kGBlocks};
   for (int i = 0; i < 3; ++i)
-    if (in11[5 + i] < 1 || (uint32_t)in11[5 + i] > full[i]) return VELO_ERR_ARG;
+    if (in12[5 + i] < 1 || (uint32_t)in12[5 + i] > full[i]) return VELO_ERR_ARG;
   ctx->cfg = velo::BatchedCfg{(uint32_t)cg, (uint32_t)mg, ft, (uint32_t)fg, fit,
-                              {(uint32_t)in11[5], (uint32_t)in11[6], (uint32_t)in11[7]},
-                              route == -1 ? 0xFFFFFFFFu : (uint32_t)route, (uint32_t)fork, (uint32_t)order};
+                              {(uint32_t)in12[5], (uint32_t)in12[6], (uint32_t)in12[7]},
+                              route == -1 ? 0xFFFFFFFFu : (uint32_t)route, (uint32_t)fork, (uint32_t)order,
+                              (uint32_t)tiny};
   ctx->tuned = true;
   ctx->source = 3;
   for (int i = 0; i < 5; ++i) ctx->tuned_ms[i] = 0.0f;
@@ -424,18 +426,19 @@ velo_status velo_context_set_config(velo_context* ctx, const int32_t* in11) {
   return VELO_OK;
 }
 
-velo_status velo_context_config(const velo_context* ctx, int32_t* out12, float* tuned_ms5) {
-  if (!ctx || !out12) return VELO_ERR_ARG;
-  out12[0] = ctx->tuned ? ctx->source : 0;
-  out12[1] = (int32_t)ctx->cfg.small_grid;
-  out12[2] = (int32_t)ctx->cfg.mid_grid;
-  out12[3] = ctx->cfg.find_threads;
-  out12[4] = (int32_t)ctx->cfg.find_grid;
-  out12[5] = ctx->cfg.fit_threads;
-  for (int i = 0; i < 3; ++i) out12[6 + i] = (int32_t)ctx->cfg.esc_grid[i];
-  out12[9] = ctx->cfg.route_hits == 0xFFFFFFFFu ? -1 : (int32_t)ctx->cfg.route_hits;
-  out12[10] = (int32_t)ctx->cfg.fork;
-  out12[11] = (int32_t)ctx->cfg.find_order;
+velo_status velo_context_config(const velo_context* ctx, int32_t* out13, float* tuned_ms5) {
+  if (!ctx || !out13) return VELO_ERR_ARG;
+  out13[0] = ctx->tuned ? ctx->source : 0;
+  out13[1] = (int32_t)ctx->cfg.small_grid;
+  out13[2] = (int32_t)ctx->cfg.mid_grid;
+  out13[3] = ctx->cfg.find_threads;
+  out13[4] = (int32_t)ctx->cfg.find_grid;
+  out13[5] = ctx->cfg.fit_threads;
+  for (int i = 0; i < 3; ++i) out13[6 + i] = (int32_t)ctx->cfg.esc_grid[i];
+  out13[9] = ctx->cfg.route_hits == 0xFFFFFFFFu ? -1 : (int32_t)ctx->cfg.route_hits;
+  out13[10] = (int32_t)ctx->cfg.fork;
+  out13[11] = (int32_t)ctx->cfg.find_order;
+  out13[12] = (int32_t)ctx->cfg.tiny;
   if (tuned_ms5)
     for (int i = 0; i < 5; ++i) tuned_ms5[i] = ctx->tuned_ms[i];
   return VELO_OK;

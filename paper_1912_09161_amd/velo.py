@@ -668,23 +668,24 @@ class Context:
     SOURCES = {0: "untuned", 1: "tuned", 2: "tune cache", 3: "set"}
 
     def config(self) -> dict:
-        out = (C.c_int32 * 12)()
+        out = (C.c_int32 * 13)()
         ms = (C.c_float * 5)()
         _check(lib().velo_context_config(self._h, out, ms))
         return dict(tuned=bool(out[0]), source=self.SOURCES.get(out[0], str(out[0])),
                     cluster_grid=out[1], mid_grid=out[2], find_threads=out[3],
                     find_grid=out[4], fit_threads=out[5], tier_grids=[out[6], out[7], out[8]],
-                    route_hits=out[9], fork=bool(out[10]), find_order=bool(out[11]),
+                    route_hits=out[9], fork=bool(out[10]), find_order=bool(out[11]), tiny=bool(out[12]),
                     tuned_ms=[float(v) for v in ms[:3]], per_item_ms=[float(ms[3]), float(ms[4])])
 
     def set_config(self, cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
-                   tier_grids=(512, 256, 128), route_hits=0, fork=False, find_order=False):
+                   tier_grids=(512, 256, 128), route_hits=0, fork=False, find_order=False, tiny=False):
         """velo_context_set_config: fixed launch shapes instead of tuning.
         route_hits: 0 no routing, -1 by the small tier's plane capacity only,
         n > 0 also events above n hits (needs find_grid == 0); find_order:
-        the first tier takes the events largest first (needs find_grid == 0)."""
-        v = (C.c_int32 * 11)(cluster_grid, mid_grid, find_threads, find_grid, fit_threads, *tier_grids,
-                             route_hits, int(fork), int(find_order))
+        the first tier takes the events largest first (needs find_grid == 0); tiny: the tiny tier
+        ahead of the small one (needs find_grid == 0, 256 lanes, no routing)."""
+        v = (C.c_int32 * 12)(cluster_grid, mid_grid, find_threads, find_grid, fit_threads, *tier_grids,
+                             route_hits, int(fork), int(find_order), int(tiny))
         _check(lib().velo_context_set_config(self._h, v))
 
     def mlp_load(self, blob: bytes):

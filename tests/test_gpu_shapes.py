@@ -11,7 +11,7 @@ of 512 to 1536, the fit with 64 to 256 lanes, the tiers that take the
 escalated events with grids from their full size down to one workgroup,
 events taken largest first by the first tier, events routed past it (by
 plane capacity, by hits, all of them) with and without the fork onto the
-context's side stream.
+context's side stream, the tiny tier ahead of the small one.
 Events of uneven occupancy and high-occupancy events (where the larger
 track-finding tiers run).
 """
@@ -43,6 +43,9 @@ def shapes():
     out += [dict(BASE, tier_grids=t) for t in TIERS]
     out += [dict(BASE, route_hits=r, fork=f, find_order=o) for r, f, o in ROUTE]
     out += [dict(BASE, find_threads=128, route_hits=3000, fork=True, find_order=True, tier_grids=(1, 1, 1))]
+    # the tiny tier ahead of the small one, alone, largest first, with one-workgroup hand-over tiers
+    out += [dict(BASE, tiny=True), dict(BASE, tiny=True, find_order=True),
+            dict(BASE, tiny=True, tier_grids=(1, 1, 1))]
     # all persistent at once
     out.append(dict(cluster_grid=2048, mid_grid=512, find_threads=256, find_grid=1024, fit_threads=128,
                     tier_grids=(16, 8, 8)))
@@ -75,7 +78,7 @@ def test_every_launch_shape_equals_oracle(orc, name, n, xl):
         assert cfg["source"] == "set" and cfg["find_grid"] == sh["find_grid"]
         assert cfg["tier_grids"] == list(sh["tier_grids"])
         assert cfg["route_hits"] == sh.get("route_hits", 0) and cfg["fork"] == sh.get("fork", False)
-        assert cfg["find_order"] == sh.get("find_order", False)
+        assert cfg["find_order"] == sh.get("find_order", False) and cfg["tiny"] == sh.get("tiny", False)
         if bufs is not None:  # stale outputs of the previous shape must be overwritten
             for k in ("n_tracks", "nhits"):
                 bufs["tracks"][k].fill_(7)
@@ -96,7 +99,9 @@ def test_set_config_rejects_bad_shapes():
                 dict(find_grid=70000), dict(tier_grids=(0, 8, 8)), dict(tier_grids=(513, 8, 8)),
                 dict(tier_grids=(16, 257, 8)), dict(tier_grids=(16, 8, 129)),
                 dict(route_hits=-2), dict(route_hits=3000, find_grid=512), dict(fork=True),
-                dict(route_hits=1, fork=2), dict(find_order=True, find_grid=512), dict(find_order=2)):
+                dict(route_hits=1, fork=2), dict(find_order=True, find_grid=512), dict(find_order=2),
+                dict(tiny=True, find_grid=512), dict(tiny=True, route_hits=-1), dict(tiny=True, find_threads=128),
+                dict(tiny=2)):
         with pytest.raises(velo.VeloError):
             ctx.set_config(**dict(BASE, **bad))
     assert ctx.config()["source"] == "untuned"
