@@ -310,9 +310,11 @@ velo_status velo_mlp_infer(const velo_mlp* mlp, const float* d_feat, uint32_t n,
    of some size; track finding: lanes per event, one workgroup per event or a
    persistent grid; fit: lanes per workgroup) by timing candidates on that
    call's batch; that call synchronises the stream.  A persistent grid is
-   chosen only if it is at least 15 % faster than one workgroup per item on
-   the tuning stream (under several busy streams one workgroup per item
-   interleaves better with the other streams' work).  Persistent grids take
+   chosen only if it is at least 15 % faster (clustering) or 10 % faster
+   (track finding, against the best per-event configuration with its
+   options) than one workgroup per item on the tuning stream (under several
+   busy streams one workgroup per item interleaves better with the other
+   streams' work).  Persistent grids take
    their items from device counters in descending size order (the orders are
    built on the device, only for the stages that use them: work stealing).
    The pipeline of a call is captured as a HIP graph and replayed on later

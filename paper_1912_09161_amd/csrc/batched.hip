@@ -332,6 +332,11 @@ namespace velo {
 // with the other streams' kernels, whereas a persistent grid holds its slots
 // until its queue drains, so a small latency gain alone does not carry over.
 constexpr float kPersistentGain = 0.85f;
+// Track finding (compared with the best per-event configuration, its options
+// included): at high occupancy a persistent grid was 16 % faster on the
+// tuning stream and 5 % faster under two streams; at nominal occupancy 1 %
+// faster on one stream and 4 % slower under twelve.
+constexpr float kPersistentGainFind = 0.90f;
 
 // Pick the launch shapes stage by stage on the live batch: clustering first
 // (its output feeds the next stage), then track finding, then the fit.
@@ -371,7 +376,10 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     ctx->tuned_ms[3] = bt[0];
     if ((e = enqueue_batched(c, best, s, fk, 1)) != hipSuccess) return e;
   }
-  // track finding: lanes per event x (one workgroup per event | persistent grid)
+  // track finding: lanes per event x (one workgroup per event | persistent
+  // grid), each side then with its hand-over tier grids (and, one workgroup
+  // per event, its options); the persistent side is taken only if it beats
+  // the best per-event configuration by kPersistentGainFind
   {
     best.find_order = 0;
     const int threads[] = {128, 256};
@@ -386,29 +394,28 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
         const int p = g != 0;
         if (t < bt[p]) { bt[p] = t; pick[p] = k; }
       }
-    const int p = bt[1] < kPersistentGain * bt[0];
-    best.find_threads = pick[p].find_threads;
-    best.find_grid = pick[p].find_grid;
-    ctx->tuned_ms[1] = bt[p];
     ctx->tuned_ms[4] = bt[0];
-    // workgroups of the tiers that take the events the small tier hands on:
+    // workgroups of the tiers that take the events the first tier hands on:
     // the smallest grids within 2 % of the best time on the tuning stream
     // (a tier's launch keeps its grid's LDS reserved until every workgroup
     // has been placed, which delays other streams' work when only a few
     // events escalate)
     const uint32_t esc[3][3] = {{kMBlocks, kLBlocks, kGBlocks}, {64, 32, 32}, {16, 8, 8}};
-    float et[3];
-    BatchedCfg k2 = best;
-    for (int i = 0; i < 3; ++i) {
-      for (int j = 0; j < 3; ++j) k2.esc_grid[j] = esc[i][j];
-      if ((e = time_stage(c, k2, fk, 2, s, 3, &et[i])) != hipSuccess) return e;
+    int pe[2] = {0, 0};
+    for (int p = 0; p < 2; ++p) {
+      float et[3];
+      BatchedCfg k2 = pick[p];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) k2.esc_grid[j] = esc[i][j];
+        if ((e = time_stage(c, k2, fk, 2, s, 3, &et[i])) != hipSuccess) return e;
+      }
+      float tb = et[0];
+      for (int i = 1; i < 3; ++i) tb = et[i] < tb ? et[i] : tb;
+      for (int i = 0; i < 3; ++i)
+        if (et[i] <= 1.02f * tb) pe[p] = i;
+      for (int j = 0; j < 3; ++j) pick[p].esc_grid[j] = esc[pe[p]][j];
+      bt[p] = tb;
     }
-    float tbest = et[0];
-    for (int i = 1; i < 3; ++i) tbest = et[i] < tbest ? et[i] : tbest;
-    int pe = 0;
-    for (int i = 0; i < 3; ++i)
-      if (et[i] <= 1.02f * tbest) pe = i;
-    for (int j = 0; j < 3; ++j) best.esc_grid[j] = esc[pe][j];
     // One workgroup per event: the tiny tier ahead of the small one (six
     // workgroups per CU for the events within its capacities; the others are
     // handed on at once or after part of their work), and, for batches that
@@ -420,33 +427,42 @@ static hipError_t autotune(velo_context* ctx, const BatchedCall& c, hipStream_t 
     // beside the small tier.  Taken only when they beat the plain sequence by
     // 1 % on the tuning stream.  The tier grids are tried again at full size,
     // which the routed events may need.
-    if (best.find_grid == 0) {
+    {
       constexpr int kNR = 7;
       const uint32_t ro[kNR][4] = {// tiny, order, route, fork
                                    {1, 0, 0, 0}, {1, 1, 0, 0}, {0, 1, 0, 0}, {0, 0, 0xFFFFFFFFu, 0},
                                    {0, 1, 0xFFFFFFFFu, 0}, {0, 0, 0xFFFFFFFFu, 1}, {0, 1, 0xFFFFFFFFu, 1}};
       const bool big = c.n_events >= 8192, can_fork = fk.side != nullptr;
-      float rbest = tbest;
-      BatchedCfg k3 = best, rpick = best;
+      float rbest = bt[0];
+      BatchedCfg k3 = pick[0], rpick = pick[0];
       for (int i = 0; i < kNR; ++i) {
-        if (ro[i][0] && best.find_threads != kSThreads) continue;
+        if (ro[i][0] && pick[0].find_threads != kSThreads) continue;
         if ((ro[i][1] || ro[i][2]) && !big) continue;
         if (ro[i][3] && !can_fork) continue;
-        for (int g = 0; g < (pe == 0 ? 1 : 2); ++g) {
+        for (int g = 0; g < (pe[0] == 0 ? 1 : 2); ++g) {
           k3.tiny = ro[i][0];
           k3.find_order = ro[i][1];
           k3.route_hits = ro[i][2];
           k3.fork = ro[i][3];
-          for (int j = 0; j < 3; ++j) k3.esc_grid[j] = esc[g == 0 ? pe : 0][j];
+          for (int j = 0; j < 3; ++j) k3.esc_grid[j] = esc[g == 0 ? pe[0] : 0][j];
           if ((e = time_stage(c, k3, fk, 2, s, 3, &t)) != hipSuccess) return e;
           if (t < rbest) { rbest = t; rpick = k3; }
         }
       }
-      if (rbest < 0.99f * tbest) {
-        best = rpick;
-        ctx->tuned_ms[1] = rbest;
+      if (rbest < 0.99f * bt[0]) {
+        pick[0] = rpick;
+        bt[0] = rbest;
       }
     }
+    const int p = bt[1] < kPersistentGainFind * bt[0];
+    best.find_threads = pick[p].find_threads;
+    best.find_grid = pick[p].find_grid;
+    for (int j = 0; j < 3; ++j) best.esc_grid[j] = pick[p].esc_grid[j];
+    best.tiny = pick[p].tiny;
+    best.find_order = pick[p].find_order;
+    best.route_hits = pick[p].route_hits;
+    best.fork = pick[p].fork;
+    ctx->tuned_ms[1] = bt[p];
     if ((e = enqueue_batched(c, best, s, fk, 2)) != hipSuccess) return e;
   }
   // fit: lanes per event
