@@ -151,3 +151,35 @@ def test_geometry_is_checked():
         ctx = C.c_void_p()
         assert L.velo_context_create(C.byref(ctx), C.byref(b), C.byref(p)) == 1
     assert L.velo_cluster(fake, fake, 2, 100, None, C.byref(hits), fake, 16, None) == 1
+
+
+def test_context_shapes_are_checked_on_the_host():
+    """velo_context_set_config checks every field and their combinations
+    (routing, fork, event order and the tiny tier need one workgroup per
+    event; the fork needs routing; the tiny tier needs 256 lanes and no
+    routing) before touching the context, and velo_context_config reports
+    what was set.  No device call is made."""
+    import paper_1912_09161_amd as velo
+    base = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
+                tier_grids=(512, 256, 128))
+    good = [dict(base), dict(base, cluster_grid=2048, find_grid=1024, tier_grids=(16, 8, 8)),
+            dict(base, route_hits=-1, fork=True, find_order=True), dict(base, route_hits=3000),
+            dict(base, tiny=True, find_order=True), dict(base, find_threads=128, route_hits=1)]
+    bad = [dict(find_threads=192), dict(fit_threads=32), dict(mid_grid=0), dict(cluster_grid=-1),
+           dict(find_grid=70000), dict(tier_grids=(0, 8, 8)), dict(tier_grids=(513, 8, 8)),
+           dict(route_hits=-2), dict(route_hits=5, find_grid=512), dict(fork=True),
+           dict(find_order=True, find_grid=512), dict(tiny=True, find_grid=512),
+           dict(tiny=True, route_hits=-1), dict(tiny=True, find_threads=128)]
+    ctx = velo.Context()
+    assert ctx.config()["source"] == "untuned"
+    for b in bad:
+        with pytest.raises(velo.VeloError):
+            ctx.set_config(**dict(base, **b))
+        assert ctx.config()["source"] == "untuned"
+    for g in good:
+        ctx.set_config(**g)
+        cfg = ctx.config()
+        assert cfg["source"] == "set"
+        for k, v in g.items():
+            assert cfg[k] == (list(v) if isinstance(v, tuple) else v), (k, cfg[k], v)
+    ctx.close()
