@@ -229,3 +229,50 @@ def test_bad_offsets(orc, name):
     np.testing.assert_array_equal(gb["hits"]["status"], np.array(exp, np.uint32))
     compare_all(gb, o, off)
     ctx.close()
+
+
+def test_tiny_tier_capacity_edges(orc):
+    """The batched form with the tiny track-finding tier ahead of the small
+    one (fixed through velo_context_set_config, alone and with the
+    largest-first order): 192 hits on one plane (the most it holds) and 193
+    (handed on at once); 192 and 193 long straight lines from the origin (its
+    active-track limit and one more); 250 lines (handed on part way, within
+    the small tier) and 340 (on to the middle tier); every event equals the
+    oracle, next to ordinary nominal events."""
+    import torch
+
+    import paper_1912_09161_amd as velo
+    from gpu_helpers import host
+
+    def grid_plane(l, n):  # n isolated pixels on plane l
+        return [word(l, 100 + 2 * (k // 600), 100 + 2 * (k % 600), 3) for k in range(n)]
+
+    def by_plane(ws):  # distinct addresses, grouped by plane
+        return sorted(dict.fromkeys(int(w) for w in ws), key=lambda w: (w >> 22) & 31)
+
+    def lines(m):
+        return [(0.0, 0.0, 0.05 * np.cos(2 * np.pi * k / m + 0.01), 0.05 * np.sin(2 * np.pi * k / m + 0.01))
+                for k in range(m)]
+    good = line_event([(0.02 * 600, 0.015 * 600, 0.02, 0.015)])
+    nom = generate("nominal", 40, first_event=1200)
+    nom_events = [nom.pixels[nom.offsets[e]:nom.offsets[e + 1]].tolist() for e in range(nom.n_events)]
+    events = [by_plane(good + grid_plane(20, 191)), by_plane(good + grid_plane(20, 192)),
+              by_plane(line_event(lines(192))), by_plane(line_event(lines(193))),
+              by_plane(line_event(lines(250))), by_plane(line_event(lines(340)))] + nom_events
+    px_np, off_np = pack(events)
+    o = orc.reconstruct(px_np, off_np, threads=8)
+    per_plane = o["hits"]["layer_nhits"].reshape(-1, 26).max(1)
+    assert list(per_plane[:6]) == [192, 193, 192, 193, 250, 340]
+    px, off = to_dev(px_np, off_np)
+    base = dict(cluster_grid=0, mid_grid=512, find_threads=256, find_grid=0, fit_threads=128,
+                tier_grids=(512, 256, 128))
+    for order in (False, True):
+        ctx = velo.Context()
+        ctx.set_config(**dict(base, tiny=True, find_order=order))
+        assert ctx.config()["tiny"]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            bufs = ctx.reconstruct(px, off, stream=stream)
+        stream.synchronize()
+        compare_all(host(bufs), o, off_np)
+        ctx.close()
